@@ -1,0 +1,96 @@
+"""Gradients of Wilson-operator actions and the su(3) force (oracle).
+
+TEST INFRASTRUCTURE.  Conventions:
+
+* complex gradients follow PyTorch: grad = dS/dRe + i dS/dIm (no 1/2);
+* for an action whose variation is dS = c0 Re( Y^dag (dD_hop) X ), the
+  coefficient of Re tr(dU_mu(x) W_mu(x)) is
+      W_mu(x) = c0 s+_mu(x) [ X(x+mu) (x) ((1 - g_mu) Y(x))^dag
+                             + ((1 + g_mu) Y(x+mu)) (x) X(x)^dag ],
+  where (a (x) b^dag)_ij = sum_spin a_{s,i} conj(b_{s,j}); one boundary sign
+  per link because the backward hop from x+mu crosses the same boundary,
+  s-_mu(x+mu) = s+_mu(x);
+* the raw link gradient is G = W^dag;
+* the force for left-multiplied variations U -> exp(eps T) U, T traceless
+  anti-hermitian, is F = TA(G U^dag) with
+  TA(A) = (A - A^dag)/2 - tr(A - A^dag)/6 * 1, so dS/deps = Re tr(T^dag F).
+
+Uses: |M psi|^2 -> c0 = -2 kappa, X = psi, Y = M psi; an upstream gradient
+g on phi = M psi -> c0 = -kappa, X = psi, Y = g; the pseudofermion action
+phi_e^dag (Mhat^dag Mhat)^-1 phi_e -> c0 = +2 kappa^2 with
+X = (X_e, D_oe X_e) and Y = (Mhat X_e, (D_eo)^dag Mhat X_e), X_e the solution.
+"""
+
+from __future__ import annotations
+
+import numpy as np
+
+from . import dirac
+
+
+def outer_spin_sum(a: np.ndarray, b: np.ndarray) -> np.ndarray:
+    """sum_s a_{s,i} conj(b_{s,j}) -> [..][3][3]."""
+    return np.einsum("...si,...sj->...ij", a, np.conj(b))
+
+
+def link_gradient(X, Y, U, c0, bc=dirac.DEFAULT_BC) -> np.ndarray:
+    """Raw gradient G_mu(x) = W_mu(x)^dag of c0 Re(Y^dag D_hop X) w.r.t. U."""
+    dims = dirac.dims_of(X)
+    G = np.zeros_like(U)
+    for mu in range(4):
+        x_up = dirac.shift(X, mu, +1)
+        y_up = dirac.shift(Y, mu, +1)
+        t1 = outer_spin_sum(x_up, dirac.spin_mul(dirac.ONE4 - dirac.GAMMA[mu], Y))
+        t2 = outer_spin_sum(dirac.spin_mul(dirac.ONE4 + dirac.GAMMA[mu], y_up), X)
+        w = c0 * dirac.sign_fwd(dims, bc, mu)[..., None, None] * (t1 + t2)
+        G[..., mu, :, :] = dirac.dagger3(w)
+    return G
+
+
+def traceless_antihermitian(a: np.ndarray) -> np.ndarray:
+    d = 0.5 * (a - dirac.dagger3(a))
+    tr = np.trace(d, axis1=-2, axis2=-1)
+    return d - (tr / 3.0)[..., None, None] * np.eye(3)
+
+
+def su3_force(G, U) -> np.ndarray:
+    """F_mu(x) = TA(G_mu(x) U_mu(x)^dag)."""
+    return traceless_antihermitian(G @ dirac.dagger3(U))
+
+
+def action_norm(psi, U, kappa, bc=dirac.DEFAULT_BC) -> float:
+    """S = sum_x |(M psi)(x)|^2."""
+    phi = dirac.wilson(psi, U, kappa, bc)
+    return float(np.vdot(phi.ravel(), phi.ravel()).real)
+
+
+def grad_psi_norm(psi, U, kappa, bc=dirac.DEFAULT_BC) -> np.ndarray:
+    """dS/dpsi for S = |M psi|^2: 2 M^dag M psi."""
+    return 2.0 * dirac.wilson(dirac.wilson(psi, U, kappa, bc), U, kappa, bc, dagger=True)
+
+
+def grad_links_norm(psi, U, kappa, bc=dirac.DEFAULT_BC) -> np.ndarray:
+    """dS/dU for S = |M psi|^2 (raw complex gradient, PyTorch convention)."""
+    phi = dirac.wilson(psi, U, kappa, bc)
+    return link_gradient(psi, phi, U, -2.0 * kappa, bc)
+
+
+def vjp(psi, U, kappa, g, bc=dirac.DEFAULT_BC):
+    """Vector-Jacobian product of phi = M psi for an upstream gradient g."""
+    gpsi = dirac.wilson(g, U, kappa, bc, dagger=True)
+    gU = link_gradient(psi, g, U, -kappa, bc)
+    return gpsi, gU
+
+
+def pseudofermion_fields(x_e, U, kappa, bc=dirac.DEFAULT_BC):
+    """(X, Y) on the full lattice for S = phi_e^dag (Mhat^dag Mhat)^-1 phi_e."""
+    x_o = dirac.moe(x_e, U, bc)
+    y_e = dirac.mhat(x_e, U, kappa, bc)
+    y_o = dirac.moe(y_e, U, bc, dagger=True)
+    return dirac.project(x_e, 0) + x_o, y_e + y_o
+
+
+def pseudofermion_force(x_e, U, kappa, bc=dirac.DEFAULT_BC):
+    """su(3) force of the pseudofermion action given its solution X_e."""
+    X, Y = pseudofermion_fields(x_e, U, kappa, bc)
+    return su3_force(link_gradient(X, Y, U, 2.0 * kappa ** 2, bc), U)

@@ -1,0 +1,56 @@
+"""12-real link compression and reduced-precision storage (oracle).
+
+TEST INFRASTRUCTURE.  A link U in SU(3) is stored by its rows 0 and 1; the
+third row follows from unitarity and det U = 1 as row2 = conj(row0 x row1)
+(cross product of the two rows).  The reconstruction is exact only on SU(3):
+a U(3) matrix with det != 1 comes back rotated by det^*.
+
+Half-precision spinor storage keeps, per site, one FP32 scale equal to the
+largest absolute value among the site's 24 reals and the 24 reals divided by
+that scale rounded to IEEE binary16; links in half precision are stored as the
+binary16 rounding of their (bounded by one) entries.
+"""
+
+from __future__ import annotations
+
+import numpy as np
+
+
+def compress(U: np.ndarray) -> np.ndarray:
+    return U[..., :2, :].copy()
+
+
+def reconstruct(rows01: np.ndarray) -> np.ndarray:
+    a = rows01[..., 0, :]
+    b = rows01[..., 1, :]
+    c = np.conj(np.stack([a[..., 1] * b[..., 2] - a[..., 2] * b[..., 1],
+                          a[..., 2] * b[..., 0] - a[..., 0] * b[..., 2],
+                          a[..., 0] * b[..., 1] - a[..., 1] * b[..., 0]], axis=-1))
+    return np.concatenate([rows01, c[..., None, :]], axis=-2)
+
+
+def round_f32(z: np.ndarray) -> np.ndarray:
+    """Round a complex128 array to complex64 and back (FP32 storage)."""
+    return z.astype(np.complex64).astype(np.complex128)
+
+
+def round_f16_links(z: np.ndarray) -> np.ndarray:
+    re = z.real.astype(np.float16).astype(np.float64)
+    im = z.imag.astype(np.float16).astype(np.float64)
+    return re + 1j * im
+
+
+def round_f16_spinor(psi: np.ndarray) -> np.ndarray:
+    """Per-site scaled binary16 storage of a canonical spinor field.
+
+    scale = max |real| over the site's 24 reals (FP32); stored value =
+    binary16(real / scale) with the division in FP32; the value seen by the
+    arithmetic is stored * scale.
+    """
+    re = psi.real.astype(np.float32)
+    im = psi.imag.astype(np.float32)
+    scale = np.maximum(np.abs(re).max(axis=(-1, -2)), np.abs(im).max(axis=(-1, -2)))
+    safe = np.where(scale > 0, scale, np.float32(1.0))[..., None, None]
+    qre = (re / safe).astype(np.float16).astype(np.float32) * safe
+    qim = (im / safe).astype(np.float16).astype(np.float32) * safe
+    return qre.astype(np.float64) + 1j * qim.astype(np.float64)
