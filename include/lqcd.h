@@ -1,0 +1,258 @@
+/*
+ * lqcd.h - C ABI of the MI355X Wilson-Dirac library (liblqcd.so).
+ *
+ * The operator is the Wilson hopping term that the paper applies on KNL in
+ * Sec. 3.3 (Fig. 4d) and calls "the generic version of the Wilson kernel";
+ * the paper does not write it out, so the definitions below are the textbook
+ * ones, stated in full:
+ *
+ *   (D_hop psi)(x) = sum_{mu=0..3} [ s+_mu(x) (1 - g_mu) U_mu(x) psi(x+mu)
+ *                                  + s-_mu(x) (1 + g_mu) U_mu(x-mu)^dag psi(x-mu) ]
+ *
+ * with mu = 0,1,2,3 = x,y,z,t, gamma matrices in the DeGrand-Rossi chiral
+ * basis (gamma5 = diag(1,1,-1,-1)), s+_mu(x) = bc[mu] on the last slice
+ * x_mu = L_mu - 1 and s-_mu(x) = bc[mu] on the first slice x_mu = 0 (else 1).
+ * D_hop^dag is the same sum with (1 - g_mu) and (1 + g_mu) exchanged; the
+ * Wilson matrix is M = 1 - kappa D_hop.  Sites have parity (x+y+z+t) mod 2;
+ * D_eo (odd -> even) and D_oe (even -> odd) are the off-diagonal blocks of
+ * D_hop, and Mhat = 1 - kappa^2 D_eo D_oe is the Schur operator on even sites.
+ * Boundary conditions are applied inside the kernels (one GPU, no halo).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Every pointer named as a field (spinor, gauge, force, workspace) is
+ *    DEVICE memory owned by the caller.  The library never allocates, frees
+ *    or retains device memory and keeps no global state besides the HIP
+ *    module.  Host pointers are named so explicitly (stats, result).
+ *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *    Every call is enqueued on it and returns without waiting, except where
+ *    a function states that it synchronises the stream.
+ *  - Return value: LQCD_OK (0) or a negative status; lqcd_strerror() gives a
+ *    text.  No C++ exception crosses this interface.  Arguments are checked
+ *    before any work is enqueued, and an invalid call enqueues nothing.
+ *  - Canonical (user) layouts, lexicographic sites with x fastest, complex
+ *    numbers as (re, im) pairs of doubles (canon_prec = LQCD_F64) or floats
+ *    (canon_prec = LQCD_F32):
+ *        spinor  complex[Lt][Lz][Ly][Lx][4 spin][3 colour]
+ *        links   complex[Lt][Lz][Ly][Lx][4 mu][3 row][3 col]
+ *    An even or odd half field in canonical form is a full-size array of
+ *    which only the sites of that parity are read or written.
+ *  - Internal layouts (opaque; sizes from the *_bytes queries) hold a half
+ *    field as tiles of 64 consecutive checkerboard sites, each tile a run of
+ *    64-lane "words" of 16 bytes so that a wavefront reads one word of 64
+ *    sites in one coalesced 1 KiB access.  A full field is the even half
+ *    followed by the odd half.  Device pointers must be 256-byte aligned.
+ *  - Geometry: dims = {Lx, Ly, Lz, Lt}, each even and >= 2; bc[mu] = +1
+ *    (periodic) or -1 (antiperiodic).
+ */
+#ifndef LQCD_H
+#define LQCD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* status codes */
+#define LQCD_OK        0
+#define LQCD_EINVAL   -1   /* bad geometry, NULL or misaligned pointer, unsupported combination */
+#define LQCD_EHIP     -2   /* HIP launch or runtime error */
+#define LQCD_ENOCONV  -3   /* solver hit maxiter; x holds the last iterate */
+#define LQCD_ENAN     -4   /* non-finite residual detected */
+#define LQCD_ESMALL   -5   /* workspace smaller than the size query returned */
+
+/* storage precisions: arithmetic is FP64 for LQCD_F64 and FP32 otherwise */
+#define LQCD_F64   0
+#define LQCD_F32   1
+#define LQCD_F16   2       /* binary16 storage, FP32 arithmetic; spinors carry
+                              one FP32 scale per site (max |real| of the site) */
+
+/* link storage: full 3x3 (18 reals) or rows 0 and 1 only (12 reals), with
+   row 2 = conj(row0 x row1) rebuilt in registers (valid for SU(3) only) */
+#define LQCD_LINK18 18
+#define LQCD_LINK12 12
+
+/* field subsets */
+#define LQCD_EVEN 0
+#define LQCD_ODD  1
+#define LQCD_FULL 2
+
+typedef struct {
+    int32_t dims[4];   /* Lx, Ly, Lz, Lt */
+    int32_t bc[4];     /* +1 periodic, -1 antiperiodic */
+} lqcd_geom_t;
+
+typedef struct {
+    int32_t iterations;        /* inner iterations performed */
+    int32_t reliable_updates;  /* FP64 true-residual recomputations */
+    int32_t status;            /* same value the call returns */
+    int32_t reserved;
+    double  true_residual;     /* ||b - A x|| / ||b|| in FP64 at exit */
+    double  iterated_residual; /* last inner-precision ||r|| / ||b|| */
+    double  seconds;           /* wall time from entry to return */
+} lqcd_cg_stats_t;
+
+/* ---------------------------------------------------------------------- */
+/* library information                                                     */
+/* ---------------------------------------------------------------------- */
+
+/* Version as 10000*major + 100*minor + patch. */
+int lqcd_version(void);
+
+/* Static text for a status code (never NULL). */
+const char *lqcd_strerror(int status);
+
+/* Last HIP error text recorded by a failing call on this thread, or "". */
+const char *lqcd_last_hip_error(void);
+
+/* ---------------------------------------------------------------------- */
+/* sizes of internal fields (0 on invalid arguments)                       */
+/* ---------------------------------------------------------------------- */
+
+/* Bytes of a spinor field in internal layout; subset EVEN/ODD = half field. */
+size_t lqcd_spinor_bytes(const lqcd_geom_t *g, int prec, int subset);
+
+/* Bytes of a gauge field (4 links per site) in internal layout.
+   Supported: (F64|F32, LINK18|LINK12) and (F16, LINK12). */
+size_t lqcd_gauge_bytes(const lqcd_geom_t *g, int prec, int link);
+
+/* ---------------------------------------------------------------------- */
+/* layout conversion (untimed set-up work)                                 */
+/* ---------------------------------------------------------------------- */
+
+/* Canonical spinor -> internal.  src is a full canonical array; for subset
+   EVEN/ODD only that parity is read and dst is a half field.  Values are
+   rounded to `prec` (F16: per-site scale, see LQCD_F16). */
+int lqcd_pack_spinor(const lqcd_geom_t *g, void *dst, const void *src_canon,
+                     int canon_prec, int prec, int subset, void *stream);
+
+/* Internal -> canonical.  For subset EVEN/ODD only sites of that parity are
+   written to dst_canon; the others are left untouched. */
+int lqcd_unpack_spinor(const lqcd_geom_t *g, void *dst_canon, const void *src,
+                       int canon_prec, int prec, int subset, void *stream);
+
+/* Canonical links -> internal (LINK12 keeps rows 0 and 1). */
+int lqcd_pack_gauge(const lqcd_geom_t *g, void *dst, const void *src_canon,
+                    int canon_prec, int prec, int link, void *stream);
+
+/* Internal links (or a force / link gradient, which is LINK18) -> canonical;
+   LINK12 input is expanded with the third-row reconstruction. */
+int lqcd_unpack_gauge(const lqcd_geom_t *g, void *dst_canon, const void *src,
+                      int canon_prec, int prec, int link, void *stream);
+
+/* ---------------------------------------------------------------------- */
+/* the operator                                                            */
+/* ---------------------------------------------------------------------- */
+
+/* Full lattice:  out = alpha * D_hop in + beta * y   (y may be NULL: beta
+   ignored).  M = 1 - kappa D_hop is alpha = -kappa, beta = 1, y = in.
+   out, in, y: full spinor fields of precision prec; U: gauge field of
+   (prec, link).  out must not alias in; it may alias y. */
+int lqcd_dslash(const lqcd_geom_t *g, void *out, const void *in, const void *y,
+                const void *U, double alpha, double beta, int prec, int link,
+                void *stream);
+
+/* Same with D_hop^dag (projectors 1 + g_mu forward, 1 - g_mu backward). */
+int lqcd_dslash_dagger(const lqcd_geom_t *g, void *out, const void *in, const void *y,
+                       const void *U, double alpha, double beta, int prec, int link,
+                       void *stream);
+
+/* Even-odd blocks: out_e = alpha * D_eo in_o + beta * y_e (lqcd_meo) and
+   out_o = alpha * D_oe in_e + beta * y_o (lqcd_moe); dagger != 0 applies the
+   corresponding block of D_hop^dag, i.e. (D_oe)^dag for meo and (D_eo)^dag
+   for moe.  Half fields; out must not alias in. */
+int lqcd_meo(const lqcd_geom_t *g, void *out_e, const void *in_o, const void *y_e,
+             const void *U, double alpha, double beta, int dagger, int prec, int link,
+             void *stream);
+int lqcd_moe(const lqcd_geom_t *g, void *out_o, const void *in_e, const void *y_o,
+             const void *U, double alpha, double beta, int dagger, int prec, int link,
+             void *stream);
+
+/* Schur operator on even sites: out_e = Mhat in_e (dagger = 0) or
+   Mhat^dag in_e (dagger != 0), Mhat^dag = 1 - kappa^2 (D_oe)^dag (D_eo)^dag.
+   tmp_o: caller's odd half field of the same precision (scratch). */
+int lqcd_mhat(const lqcd_geom_t *g, void *out_e, const void *in_e, void *tmp_o,
+              const void *U, double kappa, int dagger, int prec, int link, void *stream);
+
+/* ---------------------------------------------------------------------- */
+/* BLAS-1 with deterministic wavefront reductions                          */
+/* ---------------------------------------------------------------------- */
+
+/* Bytes of device workspace a reduction over `subset` needs. */
+size_t lqcd_reduce_workspace_bytes(const lqcd_geom_t *g, int subset);
+
+/* result[0] + i result[1] = <a, b> = sum conj(a) b over every site of the
+   subset (host array of 2 doubles).  Per-thread partials in the field's
+   arithmetic precision, wave64 and block sums in FP64, final sum over blocks
+   in a fixed order: bitwise reproducible.  Synchronises the stream. */
+int lqcd_dot(const lqcd_geom_t *g, int subset, const void *a, const void *b, int prec,
+             void *workspace, double *result, void *stream);
+
+/* *result = ||a||^2 (host double); same reduction and synchronisation. */
+int lqcd_norm2(const lqcd_geom_t *g, int subset, const void *a, int prec,
+               void *workspace, double *result, void *stream);
+
+/* y = a * x + b * y for real a, b (fields of one precision and subset). */
+int lqcd_axpby(const lqcd_geom_t *g, int subset, double a, const void *x, double b,
+               void *y, int prec, void *stream);
+
+/* dst = src with a change of storage precision (same subset). */
+int lqcd_convert(const lqcd_geom_t *g, int subset, void *dst, int dst_prec,
+                 const void *src, int src_prec, void *stream);
+
+/* ---------------------------------------------------------------------- */
+/* solver                                                                  */
+/* ---------------------------------------------------------------------- */
+
+/* Bytes of workspace lqcd_cg_solve needs for the given inner precision. */
+size_t lqcd_cg_workspace_bytes(const lqcd_geom_t *g, int inner_prec, int inner_link);
+
+/* Solve A x = b on even sites, A = Mhat^dag Mhat, by CG with reliable updates.
+ *   x_e:   FP64 even half field; in: initial guess, out: solution.
+ *   b_e:   FP64 even half field (right-hand side).
+ *   U_hi:  FP64 gauge field (link_hi reals), used for the reliable updates
+ *          (true residual b - A x recomputed in FP64).
+ *   U_lo:  gauge field of (inner_prec, inner_link) for the inner iterations;
+ *          may equal U_hi when inner_prec = LQCD_F64 and links match.
+ *   The inner loop runs CG in inner_prec with FP64 block and grid sums;
+ *   every `reliable_every` iterations (0 = only when the inner residual
+ *   reaches tol) it folds the inner solution into x_e, recomputes the true
+ *   residual in FP64 and restarts the inner residual from it, keeping the
+ *   search direction.  It stops when ||b - A x|| / ||b|| <= tol (FP64).
+ *   workspace: device memory of lqcd_cg_workspace_bytes() bytes.
+ *   stats: host struct filled on return (may be NULL).
+ * Synchronises the stream.  Returns LQCD_ENOCONV after maxiter inner
+ * iterations (x_e then holds the best iterate) and LQCD_ENAN on a non-finite
+ * residual.  A call with x_e = previous result resumes the solve. */
+int lqcd_cg_solve(const lqcd_geom_t *g, void *x_e, const void *b_e,
+                  const void *U_hi, int link_hi, const void *U_lo, int inner_prec,
+                  int inner_link, double kappa, double tol, int maxiter,
+                  int reliable_every, void *workspace, size_t workspace_bytes,
+                  lqcd_cg_stats_t *stats, void *stream);
+
+/* ---------------------------------------------------------------------- */
+/* differentiation                                                         */
+/* ---------------------------------------------------------------------- */
+
+/* Link derivative of c0 * Re(Y^dag D_hop X) for every link (owner computes,
+ * no atomics).  With
+ *   W_mu(x) = coeff * s+_mu(x) [ X(x+mu) (x) ((1-g_mu) Y(x))^dag
+ *                              + ((1+g_mu) Y(x+mu)) (x) X(x)^dag ],
+ * (a (x) b^dag)_ij = sum_spin a_{s,i} conj(b_{s,j}), the result written is
+ *   mode 1: G = W^dag, the raw complex gradient dS/dRe U + i dS/dIm U;
+ *   mode 0: F = TA(G U^dag), the su(3) force for U -> exp(eps T) U, where
+ *           TA(A) = (A - A^dag)/2 - tr(A - A^dag)/6.
+ * X, Y: full spinor fields (prec); U: gauge field (prec, link);
+ * F_out: LINK18 field of precision prec (F64 or F32); accumulate != 0 adds
+ * to F_out instead of overwriting it. */
+int lqcd_fermion_force(const lqcd_geom_t *g, void *F_out, const void *X, const void *Y,
+                       const void *U, double coeff, int mode, int accumulate,
+                       int prec, int link, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LQCD_H */

@@ -1,0 +1,332 @@
+// Internal definitions shared by the HIP translation units of liblqcd.so:
+// geometry, the tiled structure-of-arrays layouts, complex arithmetic and the
+// per-site loaders/stores for every storage precision.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <hip/hip_fp16.h>
+#include <stdint.h>
+#include <stddef.h>
+
+#include "../../include/lqcd.h"
+
+namespace lqcd {
+
+// Sites per tile: one wavefront reads one 16-byte word of 64 sites at once.
+constexpr int TILE = 64;
+constexpr int TILE_SHIFT = 6;
+constexpr int WORD = 16;
+
+// ---------------------------------------------------------------------------
+// geometry
+// ---------------------------------------------------------------------------
+
+struct Geom {
+    int L[4];      // Lx, Ly, Lz, Lt
+    int bc[4];     // +1 / -1
+    int lxh;       // Lx / 2
+    int64_t vh;    // sites per parity
+    int64_t ntiles;
+    // checkerboard-index strides of one step in y, z, t
+    int64_t sy, sz, st;
+};
+
+bool make_geom(const lqcd_geom_t *g, Geom *out);
+
+// ---------------------------------------------------------------------------
+// internal layout sizes
+// ---------------------------------------------------------------------------
+
+// Spinor tile: F64 12 words (one double2 complex each), F32 6 words (two
+// complexes per float4), F16 3 words (four complexes per 8 halves) followed
+// by 64 FP32 scales (256 bytes).
+__host__ __device__ constexpr int spinor_tile_bytes(int prec) {
+    return prec == LQCD_F64 ? 12 * TILE * WORD
+         : prec == LQCD_F32 ? 6 * TILE * WORD
+                            : 3 * TILE * WORD + TILE * 4;
+}
+
+// Link tile (one direction): F64 18 -> 9 words, F64 12 -> 6 words,
+// F32 18 -> 4 words + one 8-byte half word, F32 12 -> 3 words,
+// F16 12 -> 1 word + one 8-byte half word.
+__host__ __device__ constexpr int link_tile_bytes(int prec, int link) {
+    return prec == LQCD_F64 ? (link == 18 ? 9 : 6) * TILE * WORD
+         : prec == LQCD_F32 ? (link == 18 ? 4 * TILE * WORD + TILE * 8 : 3 * TILE * WORD)
+                            : TILE * WORD + TILE * 8;
+}
+
+inline bool valid_prec(int p) { return p == LQCD_F64 || p == LQCD_F32 || p == LQCD_F16; }
+inline bool valid_link(int prec, int link) {
+    if (link != 18 && link != 12) return false;
+    if (prec == LQCD_F16 && link != 12) return false;
+    return valid_prec(prec);
+}
+
+inline size_t half_spinor_bytes(const Geom &g, int prec) {
+    return (size_t)g.ntiles * spinor_tile_bytes(prec);
+}
+inline size_t gauge_bytes(const Geom &g, int prec, int link) {
+    return (size_t)2 * g.ntiles * 4 * link_tile_bytes(prec, link);
+}
+
+// ---------------------------------------------------------------------------
+// complex arithmetic
+// ---------------------------------------------------------------------------
+
+template <typename T>
+struct cplx {
+    T re, im;
+};
+
+template <typename T>
+__device__ __forceinline__ cplx<T> operator+(cplx<T> a, cplx<T> b) { return {a.re + b.re, a.im + b.im}; }
+template <typename T>
+__device__ __forceinline__ cplx<T> operator-(cplx<T> a, cplx<T> b) { return {a.re - b.re, a.im - b.im}; }
+template <typename T>
+__device__ __forceinline__ cplx<T> operator*(cplx<T> a, cplx<T> b) {
+    return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+}
+template <typename T>
+__device__ __forceinline__ cplx<T> scale(T s, cplx<T> a) { return {s * a.re, s * a.im}; }
+template <typename T>
+__device__ __forceinline__ cplx<T> conj(cplx<T> a) { return {a.re, -a.im}; }
+// conj(a) * b
+template <typename T>
+__device__ __forceinline__ cplx<T> cmul_conj(cplx<T> a, cplx<T> b) {
+    return {a.re * b.re + a.im * b.im, a.re * b.im - a.im * b.re};
+}
+template <typename T>
+__device__ __forceinline__ T norm2(cplx<T> a) { return a.re * a.re + a.im * a.im; }
+
+// Multiply by one of {1, -1, i, -i}, coded as 0, 1, 2, 3.
+template <int C, typename T>
+__device__ __forceinline__ cplx<T> mul_unit(cplx<T> a) {
+    if constexpr (C == 0) return a;
+    else if constexpr (C == 1) return {-a.re, -a.im};
+    else if constexpr (C == 2) return {-a.im, a.re};
+    else return {a.im, -a.re};
+}
+
+// Native vector types for 16- and 8-byte accesses.
+typedef double v2d __attribute__((ext_vector_type(2)));
+typedef float v4f __attribute__((ext_vector_type(4)));
+typedef float v2f __attribute__((ext_vector_type(2)));
+typedef uint32_t v4u __attribute__((ext_vector_type(4)));
+typedef uint32_t v2u __attribute__((ext_vector_type(2)));
+
+template <int P> struct real_of { using type = float; };
+template <> struct real_of<LQCD_F64> { using type = double; };
+
+// ---------------------------------------------------------------------------
+// per-site loads and stores, spinors (12 complexes, index spin*3 + colour)
+// ---------------------------------------------------------------------------
+
+template <int P>
+__device__ __forceinline__ void load_spinor(const char *__restrict__ base, int64_t s,
+                                            cplx<typename real_of<P>::type> v[12]) {
+    const int64_t tile = s >> TILE_SHIFT;
+    const int lane = (int)(s & (TILE - 1));
+    const char *t = base + tile * spinor_tile_bytes(P);
+    if constexpr (P == LQCD_F64) {
+        const v2d *w = reinterpret_cast<const v2d *>(t) + lane;
+#pragma unroll
+        for (int k = 0; k < 12; ++k) {
+            v2d d = w[k * TILE];
+            v[k] = {d.x, d.y};
+        }
+    } else if constexpr (P == LQCD_F32) {
+        const v4f *w = reinterpret_cast<const v4f *>(t) + lane;
+#pragma unroll
+        for (int k = 0; k < 6; ++k) {
+            v4f f = w[k * TILE];
+            v[2 * k] = {f.x, f.y};
+            v[2 * k + 1] = {f.z, f.w};
+        }
+    } else {
+        const v4u *w = reinterpret_cast<const v4u *>(t) + lane;
+        const float sc = reinterpret_cast<const float *>(t + 3 * TILE * WORD)[lane];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            v4u q = w[k * TILE];
+            uint32_t u[4] = {q.x, q.y, q.z, q.w};
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                __half2 h = *reinterpret_cast<__half2 *>(&u[j]);
+                float2 f = __half22float2(h);
+                v[4 * k + j] = {f.x * sc, f.y * sc};
+            }
+        }
+    }
+}
+
+template <int P>
+__device__ __forceinline__ void store_spinor(char *__restrict__ base, int64_t s,
+                                             const cplx<typename real_of<P>::type> v[12]) {
+    const int64_t tile = s >> TILE_SHIFT;
+    const int lane = (int)(s & (TILE - 1));
+    char *t = base + tile * spinor_tile_bytes(P);
+    if constexpr (P == LQCD_F64) {
+        v2d *w = reinterpret_cast<v2d *>(t) + lane;
+#pragma unroll
+        for (int k = 0; k < 12; ++k) w[k * TILE] = v2d{v[k].re, v[k].im};
+    } else if constexpr (P == LQCD_F32) {
+        v4f *w = reinterpret_cast<v4f *>(t) + lane;
+#pragma unroll
+        for (int k = 0; k < 6; ++k)
+            w[k * TILE] = v4f{v[2 * k].re, v[2 * k].im, v[2 * k + 1].re, v[2 * k + 1].im};
+    } else {
+        float m = 0.f;
+#pragma unroll
+        for (int k = 0; k < 12; ++k) m = fmaxf(m, fmaxf(fabsf(v[k].re), fabsf(v[k].im)));
+        const float d = m > 0.f ? m : 1.f;
+        v4u *w = reinterpret_cast<v4u *>(t) + lane;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            uint32_t u[4];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                __half2 h = __floats2half2_rn(v[4 * k + j].re / d, v[4 * k + j].im / d);
+                u[j] = *reinterpret_cast<uint32_t *>(&h);
+            }
+            w[k * TILE] = v4u{u[0], u[1], u[2], u[3]};
+        }
+        reinterpret_cast<float *>(t + 3 * TILE * WORD)[lane] = m;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// per-site loads and stores, links (9 complexes, index row*3 + col)
+// ---------------------------------------------------------------------------
+
+// Row 2 of an SU(3) matrix from rows 0 and 1: conj(row0 x row1).
+template <typename T>
+__device__ __forceinline__ void reconstruct_row2(cplx<T> u[9]) {
+    u[6] = conj(u[1] * u[5] - u[2] * u[4]);
+    u[7] = conj(u[2] * u[3] - u[0] * u[5]);
+    u[8] = conj(u[0] * u[4] - u[1] * u[3]);
+}
+
+// Address of the link tile of direction mu for parity p and site tile `tile`.
+template <int P, int LK>
+__device__ __forceinline__ const char *link_tile(const char *U, int64_t ntiles, int p,
+                                                 int64_t tile, int mu) {
+    return U + (((int64_t)p * ntiles + tile) * 4 + mu) * (int64_t)link_tile_bytes(P, LK);
+}
+
+template <int P, int LK>
+__device__ __forceinline__ void load_link(const char *__restrict__ U, int64_t ntiles, int p,
+                                          int64_t s, int mu,
+                                          cplx<typename real_of<P>::type> u[9]) {
+    const int lane = (int)(s & (TILE - 1));
+    const char *t = link_tile<P, LK>(U, ntiles, p, s >> TILE_SHIFT, mu);
+    if constexpr (P == LQCD_F64) {
+        const v2d *w = reinterpret_cast<const v2d *>(t) + lane;
+        constexpr int n = LK == 18 ? 9 : 6;
+#pragma unroll
+        for (int k = 0; k < n; ++k) {
+            v2d d = __builtin_nontemporal_load(&w[k * TILE]);
+            u[k] = {d.x, d.y};
+        }
+    } else if constexpr (P == LQCD_F32) {
+        const v4f *w = reinterpret_cast<const v4f *>(t) + lane;
+        constexpr int n4 = LK == 18 ? 4 : 3;
+#pragma unroll
+        for (int k = 0; k < n4; ++k) {
+            v4f f = __builtin_nontemporal_load(&w[k * TILE]);
+            u[2 * k] = {f.x, f.y};
+            u[2 * k + 1] = {f.z, f.w};
+        }
+        if constexpr (LK == 18) {
+            const v2f *w2 = reinterpret_cast<const v2f *>(t + 4 * TILE * WORD) + lane;
+            v2f f = __builtin_nontemporal_load(w2);
+            u[8] = {f.x, f.y};
+        }
+    } else {
+        const v4u *w = reinterpret_cast<const v4u *>(t) + lane;
+        v4u q = __builtin_nontemporal_load(w);
+        const v2u *w2 = reinterpret_cast<const v2u *>(t + TILE * WORD) + lane;
+        v2u q2 = __builtin_nontemporal_load(w2);
+        uint32_t a[6] = {q.x, q.y, q.z, q.w, q2.x, q2.y};
+#pragma unroll
+        for (int j = 0; j < 6; ++j) {
+            __half2 h = *reinterpret_cast<__half2 *>(&a[j]);
+            float2 f = __half22float2(h);
+            u[j] = {f.x, f.y};
+        }
+    }
+    if constexpr (LK == 12) reconstruct_row2(u);
+}
+
+// Store a link in the layout (rows 0, 1 only for LINK12).
+template <int P, int LK>
+__device__ __forceinline__ void store_link(char *__restrict__ U, int64_t ntiles, int p,
+                                           int64_t s, int mu,
+                                           const cplx<typename real_of<P>::type> u[9]) {
+    const int lane = (int)(s & (TILE - 1));
+    char *t = const_cast<char *>(link_tile<P, LK>(U, ntiles, p, s >> TILE_SHIFT, mu));
+    if constexpr (P == LQCD_F64) {
+        v2d *w = reinterpret_cast<v2d *>(t) + lane;
+        constexpr int n = LK == 18 ? 9 : 6;
+#pragma unroll
+        for (int k = 0; k < n; ++k) w[k * TILE] = v2d{u[k].re, u[k].im};
+    } else if constexpr (P == LQCD_F32) {
+        v4f *w = reinterpret_cast<v4f *>(t) + lane;
+        constexpr int n4 = LK == 18 ? 4 : 3;
+#pragma unroll
+        for (int k = 0; k < n4; ++k)
+            w[k * TILE] = v4f{u[2 * k].re, u[2 * k].im, u[2 * k + 1].re, u[2 * k + 1].im};
+        if constexpr (LK == 18) {
+            v2f *w2 = reinterpret_cast<v2f *>(t + 4 * TILE * WORD) + lane;
+            *w2 = v2f{u[8].re, u[8].im};
+        }
+    } else {
+        uint32_t a[6];
+#pragma unroll
+        for (int j = 0; j < 6; ++j) {
+            __half2 h = __floats2half2_rn(u[j].re, u[j].im);
+            a[j] = *reinterpret_cast<uint32_t *>(&h);
+        }
+        v4u *w = reinterpret_cast<v4u *>(t) + lane;
+        *w = v4u{a[0], a[1], a[2], a[3]};
+        v2u *w2 = reinterpret_cast<v2u *>(t + TILE * WORD) + lane;
+        *w2 = v2u{a[4], a[5]};
+    }
+}
+
+// ---------------------------------------------------------------------------
+// checkerboard coordinates
+// ---------------------------------------------------------------------------
+
+struct Coord {
+    int x, y, z, t;
+};
+
+// Site s (checkerboard index) of parity p -> coordinates.
+__device__ __forceinline__ Coord cb_coords(const Geom &g, int p, int64_t s) {
+    Coord c;
+    const int xh = (int)(s % g.lxh);
+    int64_t r = s / g.lxh;
+    c.y = (int)(r % g.L[1]);
+    r /= g.L[1];
+    c.z = (int)(r % g.L[2]);
+    c.t = (int)(r / g.L[2]);
+    c.x = 2 * xh + ((p + c.y + c.z + c.t) & 1);
+    return c;
+}
+
+// Logical block index for an XCD-aware launch: the hardware hands
+// consecutive workgroups to the 8 XCDs in turn, so block b runs on XCD b % 8;
+// renumbering gives every XCD one contiguous range of tiles (its own L2 then
+// sees the neighbouring sites of its range).  A bijection for any nblocks.
+__device__ __forceinline__ int64_t xcd_block(int64_t b, int64_t nblocks) {
+    constexpr int NX = 8;
+    const int64_t q = nblocks / NX, r = nblocks % NX;
+    const int64_t x = b % NX, k = b / NX;
+    return x * q + (x < r ? x : r) + k;
+}
+
+// HIP error bookkeeping shared by the entry points.
+void set_hip_error(hipError_t e);
+int check_launch();
+
+}  // namespace lqcd

@@ -1,0 +1,218 @@
+"""GPU parity of the hopping operator against the FP64 oracle.
+
+Bars: FP64 <= 1e-13 and FP32 <= 2e-6 relative (norm-wise over the field);
+FP32 is compared with the oracle evaluated on the FP32-rounded inputs and
+with the oracle on the FP64 inputs.  binary16 storage is compared with the
+oracle on the binary16-rounded inputs (its own output is stored in binary16
+with a per-site scale, relative precision 2^-11 per entry), bar 1e-3.
+"""
+
+import numpy as np
+import pytest
+import torch
+
+import lattice_inputs as LI
+import paper_2001_07557_amd as P
+from oracle import dirac, links
+from tests.gpu_helpers import dev, f32, host, rel
+
+pytestmark = pytest.mark.gpu
+
+KAPPA = 0.124
+TOL64 = 1e-13
+TOL32 = 2e-6
+TOL16 = 1e-3
+
+GEOMS = [
+    ((4, 4, 4, 4), (1, 1, 1, -1)),     # the 4^4 single-application workload
+    ((2, 2, 2, 2), (1, 1, 1, -1)),     # every neighbour is also the opposite neighbour
+    ((6, 4, 2, 6), (1, 1, 1, -1)),     # ragged: 144 sites per parity, 2.25 tiles
+    ((8, 6, 4, 10), (-1, 1, -1, 1)),   # anisotropic, other boundary signs
+    ((2, 4, 6, 8), (-1, -1, -1, -1)),
+]
+
+
+def fields(k, dims):
+    U, psi = LI.workload_fields(k, dims)
+    return U, psi
+
+
+@pytest.mark.parametrize("prec", [P.F64, P.F32, P.F16])
+def test_spinor_pack_round_trip(prec):
+    dims = (6, 4, 2, 6)
+    lat = P.Lattice(dims)
+    _, psi = fields(1, dims)
+    for subset in (P.EVEN, P.ODD, P.FULL):
+        f = P.pack_spinor(lat, dev(psi), prec, subset)
+        back = host(P.unpack_spinor(f))
+        want = psi if prec == P.F64 else f32(psi) if prec == P.F32 else links.round_f16_spinor(psi)
+        if subset != P.FULL:
+            want = dirac.project(want, subset)
+        assert np.array_equal(back, want)
+
+
+@pytest.mark.parametrize("prec,link", [(P.F64, 18), (P.F64, 12), (P.F32, 18), (P.F32, 12), (P.F16, 12)])
+def test_gauge_pack_round_trip(prec, link):
+    dims = (6, 4, 2, 6)
+    lat = P.Lattice(dims)
+    U, _ = fields(2, dims)
+    back = host(P.unpack_gauge(P.pack_gauge(lat, dev(U), prec, link)))
+    if prec == P.F64 and link == 18:
+        assert np.array_equal(back, U)
+    elif prec == P.F64:
+        assert np.abs(back - U).max() < 1e-14
+    elif prec == P.F32:
+        assert np.abs(back - U).max() < 2e-6
+    else:
+        assert np.abs(back - U).max() < 3e-3
+
+
+@pytest.mark.parametrize("dims,bc", GEOMS)
+@pytest.mark.parametrize("link", [18, 12])
+def test_full_dslash_fp64(dims, bc, link):
+    lat = P.Lattice(dims, bc)
+    U, psi = fields(3, dims)
+    Uf = P.pack_gauge(lat, dev(U), P.F64, link)
+    pf = P.pack_spinor(lat, dev(psi), P.F64)
+    out = P.new_spinor(lat, P.F64, P.FULL)
+    for dag in (False, True):
+        P.dslash(out, pf, Uf, 1.0, 0.0, None, dagger=dag)
+        assert rel(host(P.unpack_spinor(out)), dirac.dhop(psi, U, bc, dagger=dag)) < TOL64
+        P.wilson(out, pf, Uf, KAPPA, dagger=dag)
+        assert rel(host(P.unpack_spinor(out)), dirac.wilson(psi, U, KAPPA, bc, dagger=dag)) < TOL64
+
+
+@pytest.mark.parametrize("dims,bc", GEOMS[:3])
+@pytest.mark.parametrize("link", [18, 12])
+def test_full_dslash_fp32(dims, bc, link):
+    lat = P.Lattice(dims, bc)
+    U, psi = fields(4, dims)
+    U32, psi32 = f32(U), f32(psi)
+    Uf = P.pack_gauge(lat, dev(U).to(torch.complex64), P.F32, link)
+    pf = P.pack_spinor(lat, dev(psi).to(torch.complex64), P.F32)
+    out = P.new_spinor(lat, P.F32, P.FULL)
+    for dag in (False, True):
+        P.wilson(out, pf, Uf, KAPPA, dagger=dag)
+        got = host(P.unpack_spinor(out))
+        assert rel(got, dirac.wilson(psi32, U32, KAPPA, bc, dagger=dag)) < TOL32
+        assert rel(got, dirac.wilson(psi, U, KAPPA, bc, dagger=dag)) < TOL32
+
+
+def eo_case(prec, link, dims=(16, 16, 16, 16), k=5):
+    """The 16^4 even-odd workload with rounded copies for reduced precision."""
+    U, psi = fields(k, dims)
+    rng = np.random.default_rng(50 + k)
+    y = LI.gaussian_spinor(rng, dims)
+    if prec == P.F32:
+        Ur, psr, yr = f32(U), f32(psi), f32(y)
+        if link == 12:
+            Ur = links.reconstruct(links.compress(Ur))
+        tdt = torch.complex64
+    elif prec == P.F16:
+        Ur = links.reconstruct(links.round_f16_links(links.compress(U)))
+        psr, yr = links.round_f16_spinor(psi), links.round_f16_spinor(y)
+        tdt = torch.complex128
+    else:
+        Ur, psr, yr = U, psi, y
+        tdt = torch.complex128
+    return U, psi, y, Ur, psr, yr, tdt
+
+
+@pytest.mark.parametrize("prec,link", [(P.F64, 18), (P.F64, 12), (P.F32, 18), (P.F32, 12), (P.F16, 12)])
+def test_even_odd_16x4(prec, link):
+    dims = (16, 16, 16, 16)
+    lat = P.Lattice(dims)
+    U, psi, y, Ur, psr, yr, tdt = eo_case(prec, link, dims)
+    Uf = P.pack_gauge(lat, dev(U).to(tdt), prec, link)
+    tol = {P.F64: TOL64, P.F32: TOL32, P.F16: TOL16}[prec]
+    alpha, beta = -KAPPA ** 2, 1.0
+    for out_par, fn, ofn in ((P.EVEN, P.meo, dirac.meo), (P.ODD, P.moe, dirac.moe)):
+        inp = P.pack_spinor(lat, dev(psi).to(tdt), prec, 1 - out_par)
+        yf = P.pack_spinor(lat, dev(y).to(tdt), prec, out_par)
+        out = P.new_spinor(lat, prec, out_par)
+        for dag in (False, True):
+            fn(out, inp, Uf, 1.0, 0.0, None, dagger=dag)
+            want = ofn(dirac.project(psr, 1 - out_par), Ur, dagger=dag)
+            assert rel(host(P.unpack_spinor(out)), want) < tol
+            fn(out, inp, Uf, alpha, beta, yf, dagger=dag)
+            want = alpha * want + beta * dirac.project(yr, out_par)
+            assert rel(host(P.unpack_spinor(out)), want) < tol
+
+
+@pytest.mark.parametrize("prec,link", [(P.F64, 12), (P.F32, 12)])
+def test_schur_operator(prec, link):
+    dims = (8, 8, 8, 8)
+    lat = P.Lattice(dims)
+    U, psi, y, Ur, psr, yr, tdt = eo_case(prec, link, dims, k=6)
+    Uf = P.pack_gauge(lat, dev(U).to(tdt), prec, link)
+    x = P.pack_spinor(lat, dev(psi).to(tdt), prec, P.EVEN)
+    tmp = P.new_spinor(lat, prec, P.ODD)
+    out = P.new_spinor(lat, prec, P.EVEN)
+    tol = TOL64 if prec == P.F64 else TOL32
+    P.mhat(out, x, tmp, Uf, KAPPA)
+    assert rel(host(P.unpack_spinor(out)), dirac.mhat(dirac.project(psr, 0), Ur, KAPPA)) < tol
+    P.mhat(out, x, tmp, Uf, KAPPA, dagger=True)
+    assert rel(host(P.unpack_spinor(out)), dirac.mhat_dag(dirac.project(psr, 0), Ur, KAPPA)) < tol
+
+
+def test_full_equals_even_odd_blocks():
+    dims = (8, 4, 6, 4)
+    lat = P.Lattice(dims)
+    U, psi = fields(7, dims)
+    Uf = P.pack_gauge(lat, dev(U), P.F64, 18)
+    full = P.new_spinor(lat, P.F64, P.FULL)
+    P.dslash(full, P.pack_spinor(lat, dev(psi), P.F64), Uf)
+    e = P.new_spinor(lat, P.F64, P.EVEN)
+    o = P.new_spinor(lat, P.F64, P.ODD)
+    P.meo(e, P.pack_spinor(lat, dev(psi), P.F64, P.ODD), Uf)
+    P.moe(o, P.pack_spinor(lat, dev(psi), P.F64, P.EVEN), Uf)
+    t = P.unpack_spinor(e)
+    P.unpack_spinor(o, out=t)
+    assert np.array_equal(host(t), host(P.unpack_spinor(full)))
+
+
+def test_adjoint_dot_test_on_gpu():
+    dims = (8, 8, 8, 8)
+    lat = P.Lattice(dims)
+    U, psi = fields(8, dims)
+    phi = LI.gaussian_spinor(np.random.default_rng(3), dims)
+    Uf = P.pack_gauge(lat, dev(U), P.F64, 12)
+    a = P.pack_spinor(lat, dev(psi), P.F64)
+    b = P.pack_spinor(lat, dev(phi), P.F64)
+    da = P.new_spinor(lat, P.F64, P.FULL)
+    db = P.new_spinor(lat, P.F64, P.FULL)
+    P.dslash(da, a, Uf)
+    P.dslash(db, b, Uf, dagger=True)
+    lhs = P.dot(b, da)
+    rhs = P.dot(db, a)
+    assert abs(lhs - rhs) / abs(lhs) < 1e-13
+
+
+def test_bitwise_deterministic():
+    dims = (16, 16, 16, 16)
+    lat = P.Lattice(dims)
+    U, psi = fields(9, dims)
+    Uf = P.pack_gauge(lat, dev(U).to(torch.complex64), P.F32, 12)
+    inp = P.pack_spinor(lat, dev(psi).to(torch.complex64), P.F32, P.ODD)
+    o1 = P.new_spinor(lat, P.F32, P.EVEN)
+    o2 = P.new_spinor(lat, P.F32, P.EVEN)
+    P.meo(o1, inp, Uf)
+    for _ in range(3):
+        P.meo(o2, inp, Uf)
+    torch.cuda.synchronize()
+    assert torch.equal(o1.buf, o2.buf)
+
+
+def test_gauge_covariance_on_gpu():
+    dims = (4, 6, 4, 8)
+    lat = P.Lattice(dims)
+    U, psi = fields(10, dims)
+    om = LI.random_gauge_transform(10, dims)
+    Ug = LI.gauge_transform_links(U, om)
+    psig = LI.gauge_transform_spinor(psi, om)
+    out = P.new_spinor(lat, P.F64, P.FULL)
+    P.dslash(out, P.pack_spinor(lat, dev(psig), P.F64), P.pack_gauge(lat, dev(Ug), P.F64, 12))
+    lhs = host(P.unpack_spinor(out))
+    P.dslash(out, P.pack_spinor(lat, dev(psi), P.F64), P.pack_gauge(lat, dev(U), P.F64, 12))
+    rhs = LI.gauge_transform_spinor(host(P.unpack_spinor(out)), om)
+    assert rel(lhs, rhs) < TOL64
