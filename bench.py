@@ -1,0 +1,262 @@
+"""Benchmark of the Wilson-Dirac hot path on one MI355X.
+
+Workload (default): the even-odd Wilson hopping operator on a 16^4 lattice,
+Haar-random SU(3) links and Gaussian spinors (seeded, synthetic), kappa
+0.124, periodic in space and antiperiodic in time.  One step = 100
+back-to-back applications of the even-odd operator (D_eo on the odd half,
+then D_oe on the even half), i.e. 100 x V sites x 1320 flop.  The headline
+variant is FP32 arithmetic with 12-real links; every storage variant (FP64 and
+FP32 with 18- and 12-real links, binary16 storage) is timed the same way and
+reported under "variants".  The solve of the 32^4 smoothed-link system
+(FP64 CG vs mixed FP32 / binary16 inner solvers to a 1e-10 true residual) is
+reported under "cg".
+
+Timing: HIP events on the stream the kernels are launched on, bracketing
+exactly K steps after W warm-up steps, with device synchronisation on both
+sides.  "roofline.achieved" is the algorithmic bytes of one hop launch
+divided by the average launch duration from those events.
+"""
+
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import re
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "Dslash GFlop/s + HBM GB/s (% peak), FP64 vs FP32; CG time-to-1e-10 residual"
+PEAK_HBM = 8000.0  # GB/s, MI355X published HBM3E bandwidth
+FLOP_SITE = 1320
+# algorithmic bytes per even-odd output site: 8 links + 1 input + 1 output spinor
+BYTES_SITE = {("f64", 18): 1536, ("f64", 12): 1152, ("f32", 18): 768, ("f32", 12): 576,
+              ("f16", 12): 8 * 24 + 52 + 52}
+VARIANTS = [("f64", 18), ("f64", 12), ("f32", 18), ("f32", 12), ("f16", 12)]
+HEADLINE = ("f32", 12)
+KAPPA = 0.124
+
+
+def source_hash() -> str:
+    h = hashlib.sha256()
+    d = os.path.join(ROOT, "paper_2001_07557_amd", "csrc")
+    for f in sorted(os.listdir(d)):
+        with open(os.path.join(d, f), "rb") as fh:
+            h.update(f.encode() + fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(lattice, variant):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, or
+    None when no summary matches this kernel source and workload."""
+    name = f"meo_{variant[0]}_link{variant[1]}_{'x'.join(map(str, lattice))}_pmc.md"
+    path = os.path.join(ROOT, "profiles", name)
+    if not os.path.exists(path):
+        return None
+    text = open(path).read()
+    m_src = re.search(r"source_hash:\s*([0-9a-f]+)", text)
+    m_b = re.search(r"hbm_bytes_per_launch:\s*([0-9.eE+]+)", text)
+    if not m_src or not m_b or m_src.group(1) != source_hash():
+        return None
+    return float(m_b.group(1))
+
+
+def cpu_baseline(lattice, budget_s=15.0):
+    """The FP64 oracle's even-odd hop timed on the host on a bounded sample."""
+    import numpy as np
+
+    import lattice_inputs as LI
+    from oracle import dirac
+
+    U, psi = LI.workload_fields(1, lattice)
+    psi_o = dirac.project(psi, 1)
+    vh = LI.volume(lattice) // 2
+    n = 0
+    w0, c0 = time.perf_counter(), time.process_time()
+    while True:
+        dirac.meo(psi_o, U)
+        dirac.moe(psi, U)
+        n += 1
+        if time.perf_counter() - w0 > budget_s:
+            break
+    wall = time.perf_counter() - w0
+    cpu = time.process_time() - c0
+    return {"value": round(FLOP_SITE * 2 * vh * n / wall / 1e9, 4), "unit": "GFlop/s",
+            "cores": max(1, int(round(cpu / wall))), "kind": "oracle",
+            "sample": f"{n} applications of the even-odd operator (D_eo then D_oe) on "
+                      f"{'x'.join(map(str, lattice))}, FP64 numpy oracle, {wall:.1f} s wall"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--apps", type=int, default=100, help="applications per step")
+    ap.add_argument("--lattice", default="16,16,16,16")
+    ap.add_argument("--only", default=None, help="time one variant, e.g. f32-12")
+    ap.add_argument("--no-cg", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--cg-lattice", default="32,32,32,32")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of MIB MiB 5 times (counter calibration)")
+    args = ap.parse_args()
+    if args.calibrate_copy:
+        import torch
+        n = args.calibrate_copy << 20
+        a = torch.ones(n, dtype=torch.uint8, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(5):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_per_launch": n, "launches": 5}))
+        return
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py: this build measures the hot path on one GPU only; "
+              "the multi-GPU halo exchange is a design, not an implementation (use --gpus 1)",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import lattice_inputs as LI
+    import paper_2001_07557_amd as P
+
+    prec_of = {"f64": P.F64, "f32": P.F32, "f16": P.F16}
+    lattice = tuple(int(v) for v in args.lattice.split(","))
+    lat = P.Lattice(lattice)
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    U, psi = LI.workload_fields_device(1, lattice, dev)
+
+    variants = VARIANTS
+    if args.only:
+        p, l = args.only.split("-")
+        variants = [(p, int(l))]
+    results = {}
+    headline = None
+    for var in variants:
+        prec = prec_of[var[0]]
+        tdt = torch.complex64 if prec == P.F32 else torch.complex128
+        Uf = P.pack_gauge(lat, U.to(tdt), prec, var[1])
+        odd_in = P.pack_spinor(lat, psi.to(tdt), prec, P.ODD)
+        even_in = P.pack_spinor(lat, psi.to(tdt), prec, P.EVEN)
+        even_out = P.new_spinor(lat, prec, P.EVEN)
+        odd_out = P.new_spinor(lat, prec, P.ODD)
+
+        def step():
+            # same inputs every application, outputs overwritten
+            for _ in range(args.apps):
+                P.meo(even_out, odd_in, Uf)
+                P.moe(odd_out, even_in, Uf)
+
+        for _ in range(args.warmup):
+            step()
+        stream = torch.cuda.current_stream()
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(args.steps):
+            step()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        launches = 2 * args.apps * args.steps
+        t_launch = ms * 1e-3 / launches
+        vh = lat.half_volume
+        bytes_launch = BYTES_SITE[var] * vh
+        gflops = FLOP_SITE * vh / t_launch / 1e9
+        gbs = bytes_launch / t_launch / 1e9
+        results[f"{var[0]}-{var[1]}"] = {
+            "gflops": round(gflops, 1), "gbs": round(gbs, 1), "frac_hbm": round(gbs / PEAK_HBM, 4),
+            "us_per_launch": round(t_launch * 1e6, 3), "bytes_per_site": BYTES_SITE[var]}
+        if var == HEADLINE or args.only:
+            headline = (var, ms, t_launch, bytes_launch, gflops, gbs)
+        del Uf, odd_in, even_in, even_out, odd_out
+    del U, psi
+    torch.cuda.empty_cache()
+
+    cg = None
+    if not args.no_cg:
+        cg = run_cg(P, LI, torch, tuple(int(v) for v in args.cg_lattice.split(",")), dev)
+
+    var, ms, t_launch, bytes_launch, gflops, gbs = headline
+    traffic = measured_traffic(lattice, var)
+    line = {
+        "metric": METRIC,
+        "value": round(gflops, 1),
+        "unit": "GFlop/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms / args.steps, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": var[0],
+        "data": "synthetic",
+        "config": {
+            "workload": f"even-odd Wilson Dslash D_eo + D_oe, {'x'.join(map(str, lattice))} lattice, "
+                        f"{args.apps} applications per step, {var[0].upper()} storage, "
+                        f"{var[1]}-real links",
+            "lattice": list(lattice), "kappa": KAPPA, "bc": "periodic x,y,z; antiperiodic t",
+            "links": "Haar-random SU(3)", "flop_per_site": FLOP_SITE,
+        },
+        "roofline": {
+            "bound": "hbm", "achieved": round(gbs, 1), "peak": PEAK_HBM, "unit": "GB/s",
+            "frac": round(gbs / PEAK_HBM, 4),
+            "traffic": None if traffic is None else round(traffic / t_launch / 1e9, 1),
+        },
+        "variants": results,
+    }
+    if cg is not None:
+        line["cg"] = cg
+    if not args.no_cpu:
+        line["cpu_baseline"] = cpu_baseline(lattice)
+    print(json.dumps(line), flush=True)
+
+
+def run_cg(P, LI, torch, dims, dev):
+    """Time-to-solution at 1e-10 true residual on smoothed links."""
+    lat = P.Lattice(dims)
+    Ud, psid = LI.workload_fields_device(3, dims, dev)
+    Ud = LI.ape_smooth(Ud, steps=10, alpha=0.5)
+    U_hi = P.pack_gauge(lat, Ud, P.F64, 18)
+    b = P.pack_spinor(lat, psid, P.F64, P.EVEN)
+    out = {"lattice": list(dims), "kappa": KAPPA, "tol": 1e-10, "links": "APE-smoothed 10 x 0.5"}
+    sols = {}
+    for name, (prec, link, rel_every) in {"f64": (P.F64, 18, 0), "f32-12": (P.F32, 12, 100),
+                                          "f16-12": (P.F16, 12, 100)}.items():
+        U_lo = U_hi if prec == P.F64 else P.pack_gauge(
+            lat, Ud.to(torch.complex64) if prec == P.F32 else Ud, prec, link)
+        ws = P.cg_workspace(lat, prec, link, dev)
+        x = P.new_spinor(lat, P.F64, P.EVEN)
+        P.cg_solve(x, b, U_hi, U_lo, KAPPA, tol=1e-10, maxiter=20000,
+                   reliable_every=rel_every, workspace=ws)  # warm-up (kernel load)
+        x.buf.zero_()
+        torch.cuda.synchronize()
+        st = P.cg_solve(x, b, U_hi, U_lo, KAPPA, tol=1e-10, maxiter=20000,
+                        reliable_every=rel_every, workspace=ws)
+        sols[name] = P.unpack_spinor(x)
+        out[name] = {"seconds": round(st.seconds, 4), "iterations": st.iterations,
+                     "reliable_updates": st.reliable_updates,
+                     "true_residual": st.true_residual}
+    ref = sols["f64"]
+    for name in ("f32-12", "f16-12"):
+        out[name]["rel_err_vs_f64_solution"] = float(
+            torch.linalg.vector_norm(sols[name] - ref) / torch.linalg.vector_norm(ref))
+    out["speedup_f32_vs_f64"] = round(out["f64"]["seconds"] / out["f32-12"]["seconds"], 3)
+    out["speedup_f16_vs_f64"] = round(out["f64"]["seconds"] / out["f16-12"]["seconds"], 3)
+    return out
+
+
+if __name__ == "__main__":
+    main()

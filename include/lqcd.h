@@ -41,7 +41,8 @@
  *    field as tiles of 64 consecutive checkerboard sites, each tile a run of
  *    64-lane "words" of 16 bytes so that a wavefront reads one word of 64
  *    sites in one coalesced 1 KiB access.  A full field is the even half
- *    followed by the odd half.  Device pointers must be 256-byte aligned.
+ *    followed by the odd half.  Field pointers must be 16-byte aligned and
+ *    the solver workspace 256-byte aligned (LQCD_EINVAL otherwise).
  *  - Geometry: dims = {Lx, Ly, Lz, Lt}, each even and >= 2; bc[mu] = +1
  *    (periodic) or -1 (antiperiodic).
  */
@@ -216,11 +217,15 @@ size_t lqcd_cg_workspace_bytes(const lqcd_geom_t *g, int inner_prec, int inner_l
  *          (true residual b - A x recomputed in FP64).
  *   U_lo:  gauge field of (inner_prec, inner_link) for the inner iterations;
  *          may equal U_hi when inner_prec = LQCD_F64 and links match.
- *   The inner loop runs CG in inner_prec with FP64 block and grid sums;
- *   every `reliable_every` iterations (0 = only when the inner residual
- *   reaches tol) it folds the inner solution into x_e, recomputes the true
+ *   The inner loop runs CG in inner_prec with FP64 block and grid sums.
+ *   A reliable update folds the inner solution into x_e, recomputes the true
  *   residual in FP64 and restarts the inner residual from it, keeping the
- *   search direction.  It stops when ||b - A x|| / ||b|| <= tol (FP64).
+ *   search direction; it is taken every `reliable_every` iterations (0 =
+ *   never on a schedule), whenever an FP32/F16 inner residual has fallen by
+ *   10x since the last update (the inner recurrence is not trusted further),
+ *   and when the inner residual reaches tol.  The solve stops when
+ *   ||b - A x|| / ||b|| <= tol in FP64.  The host reads the inner residual
+ *   every 10 iterations.
  *   workspace: device memory of lqcd_cg_workspace_bytes() bytes.
  *   stats: host struct filled on return (may be NULL).
  * Synchronises the stream.  Returns LQCD_ENOCONV after maxiter inner

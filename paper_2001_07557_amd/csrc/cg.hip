@@ -2,8 +2,9 @@
 // reliable updates: the inner iteration runs in the storage precision of the
 // sloppy gauge field (FP64, FP32 or binary16 storage with FP32 arithmetic),
 // global sums are FP64 and fixed-order, and the true residual b - A x is
-// recomputed in FP64 every `reliable_every` iterations and whenever the inner
-// residual reaches the tolerance.  CG scalars live in device memory, so an
+// recomputed in FP64 every `reliable_every` iterations, whenever a
+// reduced-precision inner residual has fallen tenfold since the last update,
+// and whenever the inner residual reaches the tolerance.  CG scalars live in device memory, so an
 // iteration is a stream of kernels with no host round trip; the host reads
 // the residual only every few iterations.
 //
@@ -23,6 +24,11 @@ namespace lqcd {
 
 constexpr int CG_BLOCK = 256;
 constexpr int CHECK_EVERY = 10;
+// A reduced-precision inner recurrence is trusted only while its residual is
+// within a factor DELTA of the last true residual: past that point the
+// computed and true residuals part (rounding of the inner precision), so a
+// reliable update is taken.  FP64 inner iterations need it only at the end.
+constexpr double DELTA = 0.1;
 
 enum { S_RR = 0, S_PAP, S_ALPHA, S_RROLD, S_BETA, S_OUT, S_COUNT = 16 };
 enum { OP_ALPHA = 0, OP_RRNEW, OP_RESET, OP_SUM, OP_SETRR };
@@ -37,14 +43,17 @@ __global__ __launch_bounds__(CG_BLOCK) void cg_scalar_k(const double *partial, i
     if (threadIdx.x == 0) {
         const double s = v[0];
         if constexpr (OP == OP_ALPHA) {
+            // <p, A p> = 0 only when p = 0: the iteration has terminated
+            // exactly (e.g. a source spanned by few eigenvectors); take no step
+            // and let the next residual check confirm convergence.
             sc[S_PAP] = s;
-            sc[S_ALPHA] = sc[S_RR] / s;
+            sc[S_ALPHA] = s > 0.0 ? sc[S_RR] / s : 0.0;
         } else if constexpr (OP == OP_RRNEW || OP == OP_RESET) {
             // RRNEW: rr_old <- rr before the update; RESET keeps rr_old of the
             // iteration and replaces rr by the norm of the recomputed residual
             if constexpr (OP == OP_RRNEW) sc[S_RROLD] = sc[S_RR];
             sc[S_RR] = s;
-            sc[S_BETA] = s / sc[S_RROLD];
+            sc[S_BETA] = sc[S_RROLD] > 0.0 ? s / sc[S_RROLD] : 0.0;
         } else if constexpr (OP == OP_SETRR) {
             sc[S_RR] = s;
         } else {
@@ -300,6 +309,8 @@ struct Solver {
 
         int k = 0;
         double rr_it = rr;
+        double rr_ref = rr;  // true residual at the last reliable update
+        const double drift = P == LQCD_F64 ? 0.0 : DELTA * DELTA;
         while (true) {
             rc = apply_a(P, link, U, w.p, w.ap, w.te, w.to, w.partial);
             if (rc) return rc;
@@ -317,7 +328,7 @@ struct Solver {
                     stats->iterations = k;
                     return LQCD_ENAN;
                 }
-                if (rr_it <= target) reliable = true;
+                if (rr_it <= target || rr_it < drift * rr_ref) reliable = true;
             }
             if (reliable || k >= maxiter) {
                 cg_fold_k<P><<<grid(), CG_BLOCK, 0, st>>>(x64, w.xs, g.vh);
@@ -330,6 +341,7 @@ struct Solver {
                 if (!std::isfinite(rr)) return LQCD_ENAN;
                 if (rr <= target) return LQCD_OK;
                 if (k >= maxiter) return LQCD_ENOCONV;
+                rr_ref = rr;
                 // restart the inner residual from the FP64 one, keep p
                 launch_convert(g, 1, w.rs, P, w.r64, LQCD_F64, st);
                 rc = norm_into<OP_RESET>(w.rs, P);

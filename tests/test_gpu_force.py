@@ -1,0 +1,203 @@
+"""GPU parity of the fermion-force kernel and the autograd wrapper.
+
+Raw link gradients and su(3) forces are compared with the FP64 oracle
+(FP64 <= 1e-13, FP32 <= 2e-6 relative); the autograd function is checked
+with torch.autograd.gradcheck on 2^4 and, on the 24^4 workload, with
+central finite differences (h = 1e-6, FP64) of S = |M psi|^2 on 64 random
+site entries and 64 random link entries.  The finite differences sum
+|phi(y)|^2 only over the sites a perturbation can change, which is the same
+difference of S without the cancellation of the full-lattice sum.
+"""
+
+import numpy as np
+import pytest
+import torch
+
+import lattice_inputs as LI
+import paper_2001_07557_amd as P
+from oracle import dirac, force, links, solver
+from tests.gpu_helpers import dev, f32, host, rel
+
+pytestmark = pytest.mark.gpu
+
+KAPPA = 0.124
+
+
+@pytest.mark.parametrize("dims,bc", [((4, 4, 4, 4), (1, 1, 1, -1)), ((6, 4, 2, 6), (-1, 1, 1, -1)),
+                                     ((2, 2, 2, 2), (1, 1, 1, -1))])
+@pytest.mark.parametrize("prec,link", [(P.F64, 18), (P.F64, 12), (P.F32, 18), (P.F32, 12)])
+def test_force_kernel_vs_oracle(dims, bc, prec, link):
+    lat = P.Lattice(dims, bc)
+    U, X = LI.workload_fields(30, dims)
+    Y = LI.gaussian_spinor(np.random.default_rng(31), dims)
+    c0 = -0.37
+    if prec == P.F32:
+        Ur, Xr, Yr, tdt, tol = f32(U), f32(X), f32(Y), torch.complex64, 2e-6
+        if link == 12:
+            Ur = links.reconstruct(links.compress(Ur))
+    else:
+        Ur, Xr, Yr, tdt, tol = U, X, Y, torch.complex128, 1e-13
+    Uf = P.pack_gauge(lat, dev(U).to(tdt), prec, link)
+    Xf = P.pack_spinor(lat, dev(X).to(tdt), prec)
+    Yf = P.pack_spinor(lat, dev(Y).to(tdt), prec)
+    G = force.link_gradient(Xr, Yr, Ur, c0, bc)
+    F = force.su3_force(G, Ur)
+    got_g = host(P.unpack_gauge(P.fermion_force(Xf, Yf, Uf, c0, mode=1)))
+    assert rel(got_g, G) < tol
+    out = P.fermion_force(Xf, Yf, Uf, c0, mode=0)
+    assert rel(host(P.unpack_gauge(out)), F) < tol
+    # accumulate adds to the existing field
+    P.fermion_force(Xf, Yf, Uf, c0, mode=0, out=out, accumulate=True)
+    assert rel(host(P.unpack_gauge(out)), 2 * F) < tol
+
+
+def test_autograd_gradcheck_2x4():
+    dims = (2, 2, 2, 2)
+    lat = P.Lattice(dims)
+    U, psi = LI.workload_fields(32, dims)
+    tpsi = dev(psi).requires_grad_(True)
+    tU = dev(U).requires_grad_(True)
+    f = lambda a, b: P.wilson_matrix(a, b, KAPPA, lat, P.F64, P.LINK18)  # noqa: E731
+    assert torch.autograd.gradcheck(f, (tpsi, tU), eps=1e-6, atol=1e-8, rtol=1e-7)
+
+
+@pytest.mark.parametrize("prec,link", [(P.F64, 18), (P.F64, 12), (P.F32, 12)])
+def test_autograd_vjp_vs_oracle(prec, link):
+    dims = (8, 4, 6, 4)
+    lat = P.Lattice(dims)
+    U, psi = LI.workload_fields(33, dims)
+    g = LI.gaussian_spinor(np.random.default_rng(34), dims)
+    tdt = torch.complex64 if prec == P.F32 else torch.complex128
+    tpsi = dev(psi).to(tdt).requires_grad_(True)
+    tU = dev(U).to(tdt).requires_grad_(True)
+    phi = P.wilson_matrix(tpsi, tU, KAPPA, lat, prec, link)
+    phi.backward(dev(g).to(tdt))
+    want_phi = dirac.wilson(psi, U, KAPPA)
+    want_gpsi, want_gU = force.vjp(psi, U, KAPPA, g)
+    tol = 2e-6 if prec == P.F32 else 1e-13
+    assert rel(host(phi).astype(np.complex128), want_phi) < tol
+    assert rel(host(tpsi.grad).astype(np.complex128), want_gpsi) < tol
+    assert rel(host(tU.grad).astype(np.complex128), want_gU) < tol
+
+
+def test_autograd_su3_force_mode():
+    dims = (4, 4, 4, 4)
+    lat = P.Lattice(dims)
+    U, psi = LI.workload_fields(35, dims)
+    tpsi = dev(psi).requires_grad_(True)
+    tU = dev(U).requires_grad_(True)
+    phi = P.wilson_matrix(tpsi, tU, KAPPA, lat, P.F64, P.LINK12, link_grad="su3")
+    (phi.abs() ** 2).sum().backward()
+    want = force.su3_force(force.grad_links_norm(psi, U, KAPPA), U)
+    assert rel(host(tU.grad), want) < 1e-13
+
+
+# ----------------------------------------------------------------------------
+# the 24^4 differentiated workload
+# ----------------------------------------------------------------------------
+
+def _touched_sites(dims, site):
+    """Sites whose M psi depends on psi(site): the site and its 8 neighbours."""
+    x, y, z, t = site
+    out = {(x, y, z, t)}
+    for mu in range(4):
+        for s in (1, -1):
+            c = [x, y, z, t]
+            c[mu] = (c[mu] + s) % dims[mu]
+            out.add(tuple(c))
+    return sorted(out)
+
+
+def _local_s(phi, sites):
+    return sum(float(np.vdot(phi[t, z, y, x], phi[t, z, y, x]).real) for (x, y, z, t) in sites)
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("prec", [P.F64, P.F32])
+def test_differentiated_24x4(prec):
+    dims = (24, 24, 24, 24)
+    lat = P.Lattice(dims)
+    U, psi = LI.workload_fields(3, dims)
+    tdt = torch.complex64 if prec == P.F32 else torch.complex128
+    tpsi = dev(psi).to(tdt).requires_grad_(True)
+    tU = dev(U).to(tdt).requires_grad_(True)
+    phi = P.wilson_matrix(tpsi, tU, KAPPA, lat, prec, P.LINK12)
+    (phi.abs() ** 2).sum().backward()
+    gpsi = host(tpsi.grad).astype(np.complex128)
+    gU = host(tU.grad).astype(np.complex128)
+    # against the oracle gradient (FP64 oracle on FP64 inputs for both precisions)
+    want_gpsi = force.grad_psi_norm(psi, U, KAPPA)
+    want_gU = force.grad_links_norm(psi, U, KAPPA)
+    tol = 2e-6 if prec == P.F32 else 1e-13
+    assert rel(gpsi, want_gpsi) < tol
+    assert rel(gU, want_gU) < tol
+    if prec != P.F64:
+        return
+    # central finite differences on the GPU forward, h = 1e-6
+    rng = LI.fd_rng(4)
+    h = 1e-6
+    Ut = dev(U)
+
+    def phi_of(ps, uu):
+        with torch.no_grad():
+            return host(P.wilson_matrix(ps, uu, KAPPA, lat, P.F64, P.LINK18))
+
+    worst = 0.0
+    for _ in range(64):
+        site = tuple(int(rng.integers(0, d)) for d in dims)
+        s, c = int(rng.integers(0, 4)), int(rng.integers(0, 3))
+        part = 1.0 if rng.integers(0, 2) == 0 else 1j
+        sites = _touched_sites(dims, site)
+        idx = (site[3], site[2], site[1], site[0], s, c)
+        pp = psi.copy(); pp[idx] += part * h
+        pm = psi.copy(); pm[idx] -= part * h
+        fd = (_local_s(phi_of(dev(pp), Ut), sites) - _local_s(phi_of(dev(pm), Ut), sites)) / (2 * h)
+        an = gpsi[idx].real if part == 1.0 else gpsi[idx].imag
+        worst = max(worst, abs(fd - an) / max(1.0, abs(an)))
+    assert worst < 1e-6
+    tp = dev(psi)
+    worst = 0.0
+    for _ in range(64):
+        site = tuple(int(rng.integers(0, d)) for d in dims)
+        mu, i, j = int(rng.integers(0, 4)), int(rng.integers(0, 3)), int(rng.integers(0, 3))
+        part = 1.0 if rng.integers(0, 2) == 0 else 1j
+        up = list(site)
+        up[mu] = (up[mu] + 1) % dims[mu]
+        sites = sorted({site, tuple(up)})
+        idx = (site[3], site[2], site[1], site[0], mu, i, j)
+        Up = U.copy(); Up[idx] += part * h
+        Um = U.copy(); Um[idx] -= part * h
+        fd = (_local_s(phi_of(tp, dev(Up)), sites) - _local_s(phi_of(tp, dev(Um)), sites)) / (2 * h)
+        an = gU[idx].real if part == 1.0 else gU[idx].imag
+        worst = max(worst, abs(fd - an) / max(1.0, abs(an)))
+    assert worst < 1e-6
+
+
+@pytest.mark.slow
+def test_pseudofermion_force_pipeline_small():
+    """Solve then force on the GPU (X_e from CG, X_o, Y_e, Y_o recomputed by
+    hops) against the oracle's pseudofermion force from the same X_e."""
+    dims = (8, 8, 8, 8)
+    lat = P.Lattice(dims)
+    U, phi = LI.workload_fields(36, dims)
+    U_hi = P.pack_gauge(lat, dev(U), P.F64, 18)
+    U_lo = P.pack_gauge(lat, dev(U).to(torch.complex64), P.F32, 12)
+    b = P.pack_spinor(lat, dev(phi), P.F64, P.EVEN)
+    x = P.new_spinor(lat, P.F64, P.EVEN)
+    st = P.cg_solve(x, b, U_hi, U_lo, KAPPA, tol=1e-12)
+    assert st.iterations < 200, st
+    x_e = host(P.unpack_spinor(x))
+    # recompute X_o = D_oe X_e, Y_e = Mhat X_e, Y_o = (D_eo)^dag Y_e on the GPU
+    Xf = P.new_spinor(lat, P.F64, P.FULL)
+    Yf = P.new_spinor(lat, P.F64, P.FULL)
+    hb = lat.spinor_bytes(P.F64, P.EVEN)
+    half = lambda f, par: P.SpinorField(lat, P.F64, par, f.buf[par * hb:(par + 1) * hb])  # noqa: E731
+    P.convert(half(Xf, P.EVEN), x)
+    P.moe(half(Xf, P.ODD), x, U_hi)
+    tmp = P.new_spinor(lat, P.F64, P.ODD)
+    P.mhat(half(Yf, P.EVEN), x, tmp, U_hi, KAPPA)
+    P.moe(half(Yf, P.ODD), half(Yf, P.EVEN), U_hi, dagger=True)
+    F = host(P.unpack_gauge(P.fermion_force(Xf, Yf, U_hi, 2 * KAPPA ** 2, mode=0)))
+    want = force.pseudofermion_force(x_e, U, KAPPA)
+    assert rel(F, want) < 1e-12
+    assert solver.true_residual(x_e, dirac.project(phi, 0), U, KAPPA) <= 1e-12
