@@ -6,8 +6,8 @@ third row follows from unitarity and det U = 1 as row2 = conj(row0 x row1)
 a U(3) matrix with det != 1 comes back rotated by det^*.
 
 Half-precision spinor storage keeps, per site, one FP32 scale equal to the
-largest absolute value among the site's 24 reals and the 24 reals divided by
-that scale rounded to IEEE binary16; links in half precision are stored as the
+largest absolute value among the site's 24 reals and the 24 reals times the
+FP32 reciprocal of that scale rounded to IEEE binary16; links in half precision are stored as the
 binary16 rounding of their (bounded by one) entries.
 """
 
@@ -44,13 +44,15 @@ def round_f16_spinor(psi: np.ndarray) -> np.ndarray:
     """Per-site scaled binary16 storage of a canonical spinor field.
 
     scale = max |real| over the site's 24 reals (FP32); stored value =
-    binary16(real / scale) with the division in FP32; the value seen by the
-    arithmetic is stored * scale.
+    binary16(real * r) with r = 1/scale rounded to FP32 and the product in
+    FP32; the value seen by the arithmetic is stored * scale (FP32).
     """
     re = psi.real.astype(np.float32)
     im = psi.imag.astype(np.float32)
     scale = np.maximum(np.abs(re).max(axis=(-1, -2)), np.abs(im).max(axis=(-1, -2)))
-    safe = np.where(scale > 0, scale, np.float32(1.0))[..., None, None]
-    qre = (re / safe).astype(np.float16).astype(np.float32) * safe
-    qim = (im / safe).astype(np.float16).astype(np.float32) * safe
+    safe = np.where(scale > 0, scale, np.float32(1.0))
+    r = (np.float32(1.0) / safe).astype(np.float32)[..., None, None]
+    safe = safe[..., None, None]
+    qre = (re * r).astype(np.float16).astype(np.float32) * safe
+    qim = (im * r).astype(np.float16).astype(np.float32) * safe
     return qre.astype(np.float64) + 1j * qim.astype(np.float64)

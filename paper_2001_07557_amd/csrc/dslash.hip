@@ -17,39 +17,79 @@
 
 namespace lqcd {
 
-template <int P, int LK, bool DAG, bool HASY, bool NORM>
-__global__ __launch_bounds__(256) void hop_kernel(HopArgs a) {
+// Epilogue shared by both kernel shapes: out = alpha acc + beta y, optional |out|^2.
+template <int P, bool HASY, bool NORM>
+__device__ __forceinline__ double hop_epilogue(const HopArgs &a, int p, int64_t s,
+                                               cplx<typename real_of<P>::type> acc[12]) {
     using T = typename real_of<P>::type;
-    const int64_t nblk = gridDim.x;
-    const int64_t blk = a.xcd ? xcd_block(blockIdx.x, nblk) : (int64_t)blockIdx.x;
-    const int q = blk >= a.bpp ? 1 : 0;
-    const int p = a.par0 ^ q;
-    const int64_t s = (blk - q * a.bpp) * blockDim.x + threadIdx.x;
-    const Geom &g = a.g;
+    const T alpha = (T)a.alpha;
+    if constexpr (HASY) {
+        cplx<T> y[12];
+        load_spinor<P>(a.y[p], s, y);
+        const T beta = (T)a.beta;
+#pragma unroll
+        for (int k = 0; k < 12; ++k)
+            acc[k] = {alpha * acc[k].re + beta * y[k].re, alpha * acc[k].im + beta * y[k].im};
+    } else {
+#pragma unroll
+        for (int k = 0; k < 12; ++k) acc[k] = scale(alpha, acc[k]);
+    }
+    double nrm = 0.0;
+    if constexpr (NORM) {
+        T t = 0;
+#pragma unroll
+        for (int k = 0; k < 12; ++k) t += norm2(acc[k]);
+        nrm = (double)t;
+    }
+    store_spinor<P>(a.out[p], s, acc);
+    return nrm;
+}
 
+// Output parity and checkerboard site of this thread (block = one 64-site tile).
+__device__ __forceinline__ int64_t hop_site_index(const HopArgs &a, int lane, int &p, int64_t &blk) {
+    blk = a.xcd ? xcd_block(blockIdx.x, gridDim.x) : (int64_t)blockIdx.x;
+    const int q = blk >= a.bpp ? 1 : 0;
+    p = a.par0 ^ q;
+    return brick_tile(a, blk - q * a.bpp) * HOP_SITES + lane;
+}
+
+// 4-way shape: wave w computes both hops of direction w; waves 1..3 leave
+// their partial spinors in LDS and wave 0 adds them up.
+template <int P, int LK, bool DAG, bool HASY, bool NORM>
+__global__ __launch_bounds__(256) void hop4_kernel(HopArgs a) {
+    using T = typename real_of<P>::type;
+    __shared__ cplx<T> part[3][12][64];
+    const int lane = threadIdx.x & 63;
+    const int w = threadIdx.x >> 6;
+    int p;
+    int64_t blk;
+    const int64_t s = hop_site_index(a, lane, p, blk);
+    const Geom &g = a.g;
+    const bool active = s < g.vh;
+    cplx<T> acc[12];
+#pragma unroll
+    for (int k = 0; k < 12; ++k) acc[k] = {0, 0};
+    if (active) {
+        const Coord c = cb_coords(g, p, s);
+        switch (w) {
+            case 0: hop_direction<0, P, LK, DAG>(g, a.in[p], a.U, p, s, c, acc); break;
+            case 1: hop_direction<1, P, LK, DAG>(g, a.in[p], a.U, p, s, c, acc); break;
+            case 2: hop_direction<2, P, LK, DAG>(g, a.in[p], a.U, p, s, c, acc); break;
+            default: hop_direction<3, P, LK, DAG>(g, a.in[p], a.U, p, s, c, acc); break;
+        }
+    }
+    if (w > 0) {
+#pragma unroll
+        for (int k = 0; k < 12; ++k) part[w - 1][k][lane] = acc[k];
+    }
+    __syncthreads();
     double nrm[1] = {0.0};
-    if (s < g.vh) {
-        cplx<T> acc[12];
-        hop_site<P, LK, DAG>(g, a.in[p], a.U, p, s, acc);
-        const T alpha = (T)a.alpha;
-        if constexpr (HASY) {
-            cplx<T> y[12];
-            load_spinor<P>(a.y[p], s, y);
-            const T beta = (T)a.beta;
+    if (w == 0 && active) {
 #pragma unroll
-            for (int k = 0; k < 12; ++k)
-                acc[k] = {alpha * acc[k].re + beta * y[k].re, alpha * acc[k].im + beta * y[k].im};
-        } else {
+        for (int j = 0; j < 3; ++j)
 #pragma unroll
-            for (int k = 0; k < 12; ++k) acc[k] = scale(alpha, acc[k]);
-        }
-        if constexpr (NORM) {
-            T t = 0;
-#pragma unroll
-            for (int k = 0; k < 12; ++k) t += norm2(acc[k]);
-            nrm[0] = (double)t;
-        }
-        store_spinor<P>(a.out[p], s, acc);
+            for (int k = 0; k < 12; ++k) acc[k] = acc[k] + part[j][k][lane];
+        nrm[0] = hop_epilogue<P, HASY, NORM>(a, p, s, acc);
     }
     if constexpr (NORM) {
         block_sum<1>(nrm);
@@ -57,45 +97,146 @@ __global__ __launch_bounds__(256) void hop_kernel(HopArgs a) {
     }
 }
 
+template <int H, int P, bool DAG>
+__device__ __forceinline__ void add_staged(const cplx<typename real_of<P>::type> (*chi)[6][64],
+                                           int lane, cplx<typename real_of<P>::type> acc[12]) {
+    using T = typename real_of<P>::type;
+    cplx<T> x0[3], x1[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        x0[a] = chi[H][a][lane];
+        x1[a] = chi[H][3 + a][lane];
+    }
+    chi_accumulate<H / 2, HopSign<H, DAG>::value>(x0, x1, acc);
+}
+
+// 8-way shape: wave w computes hop w (direction w/2, forward for even w) and
+// stages the two colour vectors of its multiplied half-spinor in LDS; wave 0
+// rebuilds the four spin rows from the eight staged half-spinors.
+template <int P, int LK, bool DAG, bool HASY, bool NORM>
+__global__ __launch_bounds__(512) void hop8_kernel(HopArgs a) {
+    using T = typename real_of<P>::type;
+    __shared__ cplx<T> chi[8][6][64];
+    const int lane = threadIdx.x & 63;
+    const int w = threadIdx.x >> 6;
+    int p;
+    int64_t blk;
+    const int64_t s = hop_site_index(a, lane, p, blk);
+    const Geom &g = a.g;
+    const bool active = s < g.vh;
+    if (active) {
+        const Coord c = cb_coords(g, p, s);
+        cplx<T> x0[3], x1[3];
+        switch (w) {
+            case 0: hop_single<0, P, LK, DAG>(g, a.in[p], a.U, p, s, c, x0, x1); break;
+            case 1: hop_single<1, P, LK, DAG>(g, a.in[p], a.U, p, s, c, x0, x1); break;
+            case 2: hop_single<2, P, LK, DAG>(g, a.in[p], a.U, p, s, c, x0, x1); break;
+            case 3: hop_single<3, P, LK, DAG>(g, a.in[p], a.U, p, s, c, x0, x1); break;
+            case 4: hop_single<4, P, LK, DAG>(g, a.in[p], a.U, p, s, c, x0, x1); break;
+            case 5: hop_single<5, P, LK, DAG>(g, a.in[p], a.U, p, s, c, x0, x1); break;
+            case 6: hop_single<6, P, LK, DAG>(g, a.in[p], a.U, p, s, c, x0, x1); break;
+            default: hop_single<7, P, LK, DAG>(g, a.in[p], a.U, p, s, c, x0, x1); break;
+        }
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            chi[w][k][lane] = x0[k];
+            chi[w][3 + k][lane] = x1[k];
+        }
+    }
+    __syncthreads();
+    double nrm[1] = {0.0};
+    if (w == 0 && active) {
+        cplx<T> acc[12];
+#pragma unroll
+        for (int k = 0; k < 12; ++k) acc[k] = {0, 0};
+        add_staged<0, P, DAG>(chi, lane, acc);
+        add_staged<1, P, DAG>(chi, lane, acc);
+        add_staged<2, P, DAG>(chi, lane, acc);
+        add_staged<3, P, DAG>(chi, lane, acc);
+        add_staged<4, P, DAG>(chi, lane, acc);
+        add_staged<5, P, DAG>(chi, lane, acc);
+        add_staged<6, P, DAG>(chi, lane, acc);
+        add_staged<7, P, DAG>(chi, lane, acc);
+        nrm[0] = hop_epilogue<P, HASY, NORM>(a, p, s, acc);
+    }
+    if constexpr (NORM) {
+        block_sum<1>(nrm);
+        if (threadIdx.x == 0) a.partial[blk] = nrm[0];
+    }
+}
+
+constexpr int hop_shape(int prec) {
+    return prec == LQCD_F64 ? LQCD_HOP_SHAPE_F64 : prec == LQCD_F32 ? LQCD_HOP_SHAPE_F32
+                                                                     : LQCD_HOP_SHAPE_F16;
+}
+
+template <int P, int LK, bool DAG, bool HASY, bool NORM>
+static void launch_shape(const HopArgs &a, dim3 grid, hipStream_t st) {
+    if constexpr (hop_shape(P) == 8) hop8_kernel<P, LK, DAG, HASY, NORM><<<grid, 512, 0, st>>>(a);
+    else hop4_kernel<P, LK, DAG, HASY, NORM><<<grid, 256, 0, st>>>(a);
+}
+
 template <int P, int LK, bool DAG>
-static void launch_p(const HopArgs &a, bool hasy, bool norm, dim3 grid, dim3 block, hipStream_t st) {
+static void launch_p(const HopArgs &a, bool hasy, bool norm, dim3 grid, hipStream_t st) {
     if (hasy) {
-        if (norm) hop_kernel<P, LK, DAG, true, true><<<grid, block, 0, st>>>(a);
-        else hop_kernel<P, LK, DAG, true, false><<<grid, block, 0, st>>>(a);
+        if (norm) launch_shape<P, LK, DAG, true, true>(a, grid, st);
+        else launch_shape<P, LK, DAG, true, false>(a, grid, st);
     } else {
-        if (norm) hop_kernel<P, LK, DAG, false, true><<<grid, block, 0, st>>>(a);
-        else hop_kernel<P, LK, DAG, false, false><<<grid, block, 0, st>>>(a);
+        if (norm) launch_shape<P, LK, DAG, false, true>(a, grid, st);
+        else launch_shape<P, LK, DAG, false, false>(a, grid, st);
     }
 }
 
 template <int P, int LK>
-static void launch_l(const HopArgs &a, bool dag, bool hasy, bool norm, dim3 grid, dim3 block,
-                     hipStream_t st) {
-    if (dag) launch_p<P, LK, true>(a, hasy, norm, grid, block, st);
-    else launch_p<P, LK, false>(a, hasy, norm, grid, block, st);
+static void launch_l(const HopArgs &a, bool dag, bool hasy, bool norm, dim3 grid, hipStream_t st) {
+    if (dag) launch_p<P, LK, true>(a, hasy, norm, grid, st);
+    else launch_p<P, LK, false>(a, hasy, norm, grid, st);
+}
+
+// Brick height for the blocked traversal: the largest bz dividing Lz with
+// three t-slices of a brick of input spinors within the L2 budget (0 = plain
+// order).  Needs whole tiles per (z,t) plane.  Measured: the blocked order
+// pays off for FP64, whose input slices overflow an XCD's L2; FP32 and
+// binary16 re-reads are served well enough by the 256 MB Infinity Cache that
+// the plain order is as fast or faster.
+static int brick_height(const Geom &g, int prec, int *plane_tiles) {
+    *plane_tiles = 0;
+    if (!LQCD_HOP_BRICK || prec != LQCD_F64) return 0;
+    const int64_t plane = (int64_t)g.lxh * g.L[1];
+    if (plane % TILE != 0 || g.vh % TILE != 0) return 0;
+    const int64_t pt = plane / TILE;
+    const int64_t slice_bytes = pt * spinor_tile_bytes(prec);
+    for (int bz = g.L[2] - 1; bz >= 1; --bz) {
+        if (g.L[2] % bz == 0 && 3 * bz * slice_bytes <= BRICK_L2_BUDGET) {
+            *plane_tiles = (int)pt;
+            return bz;
+        }
+    }
+    return 0;
 }
 
 int hop_launch(const HopArgs &a0, int prec, int link, bool dag, int nparity, hipStream_t st) {
     HopArgs a = a0;
-    const int bs = HOP_BLOCK;
-    a.bpp = (a.g.vh + bs - 1) / bs;
-    dim3 grid((unsigned)(a.bpp * nparity)), block(bs);
+    a.bpp = (a.g.vh + HOP_SITES - 1) / HOP_SITES;
+    a.xcd = a.xcd && LQCD_HOP_XCD;
+    a.bz = brick_height(a.g, prec, &a.plane_tiles);
+    dim3 grid((unsigned)(a.bpp * nparity));
     const bool hasy = a.y[0] != nullptr || a.y[1] != nullptr;
     const bool norm = a.partial != nullptr;
     if (prec == LQCD_F64) {
-        if (link == 18) launch_l<LQCD_F64, 18>(a, dag, hasy, norm, grid, block, st);
-        else launch_l<LQCD_F64, 12>(a, dag, hasy, norm, grid, block, st);
+        if (link == 18) launch_l<LQCD_F64, 18>(a, dag, hasy, norm, grid, st);
+        else launch_l<LQCD_F64, 12>(a, dag, hasy, norm, grid, st);
     } else if (prec == LQCD_F32) {
-        if (link == 18) launch_l<LQCD_F32, 18>(a, dag, hasy, norm, grid, block, st);
-        else launch_l<LQCD_F32, 12>(a, dag, hasy, norm, grid, block, st);
+        if (link == 18) launch_l<LQCD_F32, 18>(a, dag, hasy, norm, grid, st);
+        else launch_l<LQCD_F32, 12>(a, dag, hasy, norm, grid, st);
     } else {
-        launch_l<LQCD_F16, 12>(a, dag, hasy, norm, grid, block, st);
+        launch_l<LQCD_F16, 12>(a, dag, hasy, norm, grid, st);
     }
     return check_launch();
 }
 
 int64_t hop_partials(const Geom &g, int nparity) {
-    return ((g.vh + HOP_BLOCK - 1) / HOP_BLOCK) * nparity;
+    return ((g.vh + HOP_SITES - 1) / HOP_SITES) * nparity;
 }
 
 }  // namespace lqcd

@@ -5,7 +5,39 @@
 
 namespace lqcd {
 
-constexpr int HOP_BLOCK = 128;
+// Kernel shapes.  Both give a block 64 output sites (one tile):
+//   4-way: 256 threads, wave w computes the two hops of direction w and the
+//          partial spinors meet in LDS (FP64 and binary16 storage);
+//   8-way: 512 threads, wave w computes hop w alone and stages the two colour
+//          vectors of its multiplied half-spinor in LDS, where wave 0 rebuilds
+//          the four spin rows (FP32 storage).
+// Measured on gfx950 against one thread per site: the split shapes win at
+// every size (more waves in flight, shorter dependent load chains), 8-way is
+// ahead for FP32 and 4-way for FP64 and binary16 (fewer LDS bytes per hop).
+// The LQCD_HOP_SHAPE_* macros exist for ablation builds.
+#ifndef LQCD_HOP_SHAPE_F64
+#define LQCD_HOP_SHAPE_F64 4
+#endif
+#ifndef LQCD_HOP_SHAPE_F32
+#define LQCD_HOP_SHAPE_F32 8
+#endif
+#ifndef LQCD_HOP_SHAPE_F16
+#define LQCD_HOP_SHAPE_F16 4
+#endif
+// XCD-aware block numbering (ablation switch)
+#ifndef LQCD_HOP_XCD
+#define LQCD_HOP_XCD 1
+#endif
+// brick traversal for FP64 (ablation switch)
+#ifndef LQCD_HOP_BRICK
+#define LQCD_HOP_BRICK 1
+#endif
+
+constexpr int HOP_SITES = 64;  // output sites per block
+
+// Largest L2 footprint (bytes) the brick traversal plans for per XCD: three
+// t-slices of one brick of input spinors.
+constexpr int64_t BRICK_L2_BUDGET = 3 << 20;
 
 // Ends one hop: the accumulator is pinned in registers (an empty asm that
 // reads and writes it) and the scheduler may not move instructions across.
@@ -30,7 +62,26 @@ struct HopArgs {
     int64_t bpp;          // blocks per parity
     int par0;             // parity of the first bpp blocks
     int xcd;              // XCD-aware block renumbering
+    // cache-blocked traversal: tiles per (z,t) plane, z-planes per brick
+    // (0 = plain tile order)
+    int plane_tiles, bz;
 };
+
+// Tile visited by logical block b (within one parity).  With bricks of bz
+// z-planes the order is (z-brick, t, z in brick, tile in plane): the three
+// t-slices of a brick that one output slice touches stay in the XCD's L2,
+// where the plain order would revisit each input slice from memory for the
+// t-neighbours of the slices before and after it.
+__device__ __forceinline__ int64_t brick_tile(const HopArgs &a, int64_t b) {
+    if (a.bz == 0) return b;
+    const int64_t pt = b % a.plane_tiles;
+    int64_t r = b / a.plane_tiles;
+    const int64_t zi = r % a.bz;
+    r /= a.bz;
+    const int64_t t = r % a.g.L[3];
+    const int64_t zc = r / a.g.L[3];
+    return ((t * a.g.L[2] + zc * a.bz + zi) * a.plane_tiles) + pt;
+}
 
 int hop_launch(const HopArgs &a, int prec, int link, bool dag, int nparity, hipStream_t st);
 int64_t hop_partials(const Geom &g, int nparity);
@@ -63,15 +114,14 @@ __device__ __forceinline__ void project_half(const cplx<T> psi[12], cplx<T> h0[3
     }
 }
 
-// Project, multiply by U (or U^dag) and accumulate one hop into acc.
+// Project with (1 + S g_mu), apply the boundary sign and multiply by U (or
+// U^dag): the two colour vectors chi0, chi1 of one hop.
 template <int MU, int S, bool UDAG, typename T>
-__device__ __forceinline__ void hop_accumulate(const cplx<T> psi[12], const cplx<T> u[9], T sign,
-                                               cplx<T> acc[12]) {
+__device__ __forceinline__ void hop_chi(const cplx<T> psi[12], const cplx<T> u[9], T sign,
+                                        cplx<T> x0[3], cplx<T> x1[3]) {
     using PR = Proj<MU>;
     constexpr int k0 = S > 0 ? PR::c0 : neg_code(PR::c0);
     constexpr int k1 = S > 0 ? PR::c1 : neg_code(PR::c1);
-    constexpr int r0 = S > 0 ? conj_code(PR::c0) : neg_code(conj_code(PR::c0));
-    constexpr int r1 = S > 0 ? conj_code(PR::c1) : neg_code(conj_code(PR::c1));
     cplx<T> h0[3], h1[3];
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
@@ -80,20 +130,92 @@ __device__ __forceinline__ void hop_accumulate(const cplx<T> psi[12], const cplx
     }
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-        cplx<T> x0, x1;
         if constexpr (UDAG) {
-            x0 = cmul_conj(u[a], h0[0]) + cmul_conj(u[3 + a], h0[1]) + cmul_conj(u[6 + a], h0[2]);
-            x1 = cmul_conj(u[a], h1[0]) + cmul_conj(u[3 + a], h1[1]) + cmul_conj(u[6 + a], h1[2]);
+            x0[a] = cmul_conj(u[a], h0[0]) + cmul_conj(u[3 + a], h0[1]) + cmul_conj(u[6 + a], h0[2]);
+            x1[a] = cmul_conj(u[a], h1[0]) + cmul_conj(u[3 + a], h1[1]) + cmul_conj(u[6 + a], h1[2]);
         } else {
-            x0 = u[3 * a] * h0[0] + u[3 * a + 1] * h0[1] + u[3 * a + 2] * h0[2];
-            x1 = u[3 * a] * h1[0] + u[3 * a + 1] * h1[1] + u[3 * a + 2] * h1[2];
+            x0[a] = u[3 * a] * h0[0] + u[3 * a + 1] * h0[1] + u[3 * a + 2] * h0[2];
+            x1[a] = u[3 * a] * h1[0] + u[3 * a + 1] * h1[1] + u[3 * a + 2] * h1[2];
         }
-        acc[a] = acc[a] + x0;
-        acc[3 + a] = acc[3 + a] + x1;
-        acc[PR::a0 * 3 + a] = acc[PR::a0 * 3 + a] + mul_unit<r0>(x0);
-        acc[PR::a1 * 3 + a] = acc[PR::a1 * 3 + a] + mul_unit<r1>(x1);
     }
 }
+
+// Add one hop's chi0, chi1 into the four spin rows of acc.
+template <int MU, int S, typename T>
+__device__ __forceinline__ void chi_accumulate(const cplx<T> x0[3], const cplx<T> x1[3],
+                                               cplx<T> acc[12]) {
+    using PR = Proj<MU>;
+    constexpr int r0 = S > 0 ? conj_code(PR::c0) : neg_code(conj_code(PR::c0));
+    constexpr int r1 = S > 0 ? conj_code(PR::c1) : neg_code(conj_code(PR::c1));
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        acc[a] = acc[a] + x0[a];
+        acc[3 + a] = acc[3 + a] + x1[a];
+        acc[PR::a0 * 3 + a] = acc[PR::a0 * 3 + a] + mul_unit<r0>(x0[a]);
+        acc[PR::a1 * 3 + a] = acc[PR::a1 * 3 + a] + mul_unit<r1>(x1[a]);
+    }
+}
+
+// Project, multiply by U (or U^dag) and accumulate one hop into acc.
+template <int MU, int S, bool UDAG, typename T>
+__device__ __forceinline__ void hop_accumulate(const cplx<T> psi[12], const cplx<T> u[9], T sign,
+                                               cplx<T> acc[12]) {
+    cplx<T> x0[3], x1[3];
+    hop_chi<MU, S, UDAG>(psi, u, sign, x0, x1);
+    chi_accumulate<MU, S>(x0, x1, acc);
+}
+
+// Neighbour index and boundary sign of one hop (FWD: x + mu, else x - mu).
+template <int MU, bool FWD>
+__device__ __forceinline__ int64_t hop_neighbour(const Geom &g, int64_t s, const Coord &c, bool &flip) {
+    if constexpr (MU == 0) {
+        const int64_t row = s - (c.x >> 1);
+        if constexpr (FWD) {
+            flip = c.x == g.L[0] - 1 && g.bc[0] < 0;
+            return row + ((c.x + 1 == g.L[0] ? 0 : c.x + 1) >> 1);
+        } else {
+            flip = c.x == 0 && g.bc[0] < 0;
+            return row + ((c.x == 0 ? g.L[0] - 1 : c.x - 1) >> 1);
+        }
+    } else {
+        const int xm = MU == 1 ? c.y : MU == 2 ? c.z : c.t;
+        const int L = g.L[MU];
+        const int64_t st = MU == 1 ? g.sy : MU == 2 ? g.sz : g.st;
+        if constexpr (FWD) {
+            flip = xm == L - 1 && g.bc[MU] < 0;
+            return xm == L - 1 ? s - (int64_t)(L - 1) * st : s + st;
+        } else {
+            flip = xm == 0 && g.bc[MU] < 0;
+            return xm == 0 ? s + (int64_t)(L - 1) * st : s - st;
+        }
+    }
+}
+
+// chi of the single hop H (0..7: direction H/2, forward for even H) of site s.
+template <int H, int P, int LK, bool DAG>
+__device__ __forceinline__ void hop_single(const Geom &g, const char *__restrict__ in,
+                                           const char *__restrict__ U, int p, int64_t s,
+                                           const Coord &c, cplx<typename real_of<P>::type> x0[3],
+                                           cplx<typename real_of<P>::type> x1[3]) {
+    using T = typename real_of<P>::type;
+    constexpr int MU = H >> 1;
+    constexpr bool FWD = (H & 1) == 0;
+    constexpr int S = FWD ? (DAG ? 1 : -1) : (DAG ? -1 : 1);
+    bool flip;
+    const int64_t nb = hop_neighbour<MU, FWD>(g, s, c, flip);
+    cplx<T> psi[12], u[9];
+    T sgn = flip ? T(-1) : T(1);
+    load_spinor_hop<P>(in, nb, psi, sgn);
+    if constexpr (FWD) load_link<P, LK>(U, g.ntiles, p, s, MU, u);
+    else load_link<P, LK>(U, g.ntiles, p ^ 1, nb, MU, u);
+    hop_chi<MU, S, !FWD>(psi, u, sgn, x0, x1);
+}
+
+// Sign S of the projector of hop H.
+template <int H, bool DAG>
+struct HopSign {
+    static constexpr int value = (H & 1) == 0 ? (DAG ? 1 : -1) : (DAG ? -1 : 1);
+};
 
 // Forward and backward hops in direction MU for the site s of parity p.
 template <int MU, int P, int LK, bool DAG>
@@ -104,55 +226,25 @@ __device__ __forceinline__ void hop_direction(const Geom &g, const char *__restr
     // forward hop uses (1 - g) (S = -1), backward (1 + g); the adjoint swaps them
     constexpr int SF = DAG ? 1 : -1;
     constexpr int SB = -SF;
-    int64_t fwd, bwd;
-    bool at_last, at_first;
-    if constexpr (MU == 0) {
-        const int64_t row = s - (c.x >> 1);
-        const int xp = c.x + 1 == g.L[0] ? 0 : c.x + 1;
-        const int xm = c.x == 0 ? g.L[0] - 1 : c.x - 1;
-        fwd = row + (xp >> 1);
-        bwd = row + (xm >> 1);
-        at_last = c.x == g.L[0] - 1;
-        at_first = c.x == 0;
-    } else {
-        const int xm = MU == 1 ? c.y : MU == 2 ? c.z : c.t;
-        const int L = g.L[MU];
-        const int64_t st = MU == 1 ? g.sy : MU == 2 ? g.sz : g.st;
-        at_last = xm == L - 1;
-        at_first = xm == 0;
-        fwd = at_last ? s - (int64_t)(L - 1) * st : s + st;
-        bwd = at_first ? s + (int64_t)(L - 1) * st : s - st;
-    }
-    const T sgn_f = (at_last && g.bc[MU] < 0) ? T(-1) : T(1);
-    const T sgn_b = (at_first && g.bc[MU] < 0) ? T(-1) : T(1);
+    bool flip_f, flip_b;
+    const int64_t fwd = hop_neighbour<MU, true>(g, s, c, flip_f);
+    const int64_t bwd = hop_neighbour<MU, false>(g, s, c, flip_b);
     {
+        T sgn = flip_f ? T(-1) : T(1);
         cplx<T> psi[12], u[9];
-        load_spinor<P>(in, fwd, psi);
+        load_spinor_hop<P>(in, fwd, psi, sgn);
         load_link<P, LK>(U, g.ntiles, p, s, MU, u);
-        hop_accumulate<MU, SF, false>(psi, u, sgn_f, acc);
+        hop_accumulate<MU, SF, false>(psi, u, sgn, acc);
     }
     hop_fence(acc);
     {
+        T sgn = flip_b ? T(-1) : T(1);
         cplx<T> psi[12], u[9];
-        load_spinor<P>(in, bwd, psi);
+        load_spinor_hop<P>(in, bwd, psi, sgn);
         load_link<P, LK>(U, g.ntiles, p ^ 1, bwd, MU, u);
-        hop_accumulate<MU, SB, true>(psi, u, sgn_b, acc);
+        hop_accumulate<MU, SB, true>(psi, u, sgn, acc);
     }
     hop_fence(acc);
-}
-
-// acc = (D_hop in)(x) (or D_hop^dag) for the site s of parity p.
-template <int P, int LK, bool DAG>
-__device__ __forceinline__ void hop_site(const Geom &g, const char *__restrict__ in,
-                                         const char *__restrict__ U, int p, int64_t s,
-                                         cplx<typename real_of<P>::type> acc[12]) {
-#pragma unroll
-    for (int k = 0; k < 12; ++k) acc[k] = {0, 0};
-    const Coord c = cb_coords(g, p, s);
-    hop_direction<0, P, LK, DAG>(g, in, U, p, s, c, acc);
-    hop_direction<1, P, LK, DAG>(g, in, U, p, s, c, acc);
-    hop_direction<2, P, LK, DAG>(g, in, U, p, s, c, acc);
-    hop_direction<3, P, LK, DAG>(g, in, U, p, s, c, acc);
 }
 
 }  // namespace lqcd

@@ -159,6 +159,35 @@ __device__ __forceinline__ void load_spinor(const char *__restrict__ base, int64
     }
 }
 
+// Load for a hop: binary16 storage returns the stored (unscaled) values and
+// multiplies `factor` by the site's scale, which the hop then applies to the
+// projected half-spinor (12 products instead of 24).
+template <int P>
+__device__ __forceinline__ void load_spinor_hop(const char *__restrict__ base, int64_t s,
+                                                cplx<typename real_of<P>::type> v[12],
+                                                typename real_of<P>::type &factor) {
+    if constexpr (P == LQCD_F16) {
+        const int64_t tile = s >> TILE_SHIFT;
+        const int lane = (int)(s & (TILE - 1));
+        const char *t = base + tile * spinor_tile_bytes(P);
+        const v4u *w = reinterpret_cast<const v4u *>(t) + lane;
+        factor *= reinterpret_cast<const float *>(t + 3 * TILE * WORD)[lane];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            v4u q = w[k * TILE];
+            uint32_t u[4] = {q.x, q.y, q.z, q.w};
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                __half2 h = *reinterpret_cast<__half2 *>(&u[j]);
+                float2 f = __half22float2(h);
+                v[4 * k + j] = {f.x, f.y};
+            }
+        }
+    } else {
+        load_spinor<P>(base, s, v);
+    }
+}
+
 template <int P>
 __device__ __forceinline__ void store_spinor(char *__restrict__ base, int64_t s,
                                              const cplx<typename real_of<P>::type> v[12]) {
@@ -178,14 +207,15 @@ __device__ __forceinline__ void store_spinor(char *__restrict__ base, int64_t s,
         float m = 0.f;
 #pragma unroll
         for (int k = 0; k < 12; ++k) m = fmaxf(m, fmaxf(fabsf(v[k].re), fabsf(v[k].im)));
-        const float d = m > 0.f ? m : 1.f;
+        // stored value = binary16(real * (1/m)), the reciprocal rounded once in FP32
+        const float inv = 1.f / (m > 0.f ? m : 1.f);
         v4u *w = reinterpret_cast<v4u *>(t) + lane;
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
             uint32_t u[4];
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
-                __half2 h = __floats2half2_rn(v[4 * k + j].re / d, v[4 * k + j].im / d);
+                __half2 h = __floats2half2_rn(v[4 * k + j].re * inv, v[4 * k + j].im * inv);
                 u[j] = *reinterpret_cast<uint32_t *>(&h);
             }
             w[k * TILE] = v4u{u[0], u[1], u[2], u[3]};

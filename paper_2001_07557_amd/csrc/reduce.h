@@ -8,7 +8,7 @@
 
 namespace lqcd {
 
-constexpr int MAX_BLOCK = 256;
+constexpr int MAX_BLOCK = 512;
 constexpr int MAX_WAVES = MAX_BLOCK / 64;
 
 __device__ __forceinline__ double wave_sum(double v) {

@@ -20,3 +20,20 @@ def rel(a, b):
 def f32(z):
     """Round complex128 -> complex64 -> complex128 (the FP32 input the GPU sees)."""
     return z.astype(np.complex64).astype(np.complex128)
+
+
+class DeviceGather:
+    """Read-only array view of a device tensor: fancy-index reads gather on
+    the device and return host numpy arrays, so per-site oracle routines can
+    sample lattices too large to copy to the host."""
+
+    def __init__(self, t):
+        self.t = t
+        self.shape = tuple(t.shape)
+
+    def __getitem__(self, idx):
+        if not isinstance(idx, tuple):
+            idx = (idx,)
+        idx = tuple(torch.as_tensor(np.asarray(i), device=self.t.device)
+                    if isinstance(i, np.ndarray) else i for i in idx)
+        return self.t[idx].cpu().numpy()

@@ -216,3 +216,82 @@ def test_gauge_covariance_on_gpu():
     P.dslash(out, P.pack_spinor(lat, dev(psi), P.F64), P.pack_gauge(lat, dev(U), P.F64, 12))
     rhs = LI.gauge_transform_spinor(host(P.unpack_spinor(out)), om)
     assert rel(lhs, rhs) < TOL64
+
+
+def test_hip_graph_replays_match_eager():
+    """The even-odd step captured in a HIP graph and replayed several times,
+    with eager work and synchronisation in between, gives the eager result
+    bit for bit on every replay."""
+    dims = (8, 8, 8, 8)
+    lat = P.Lattice(dims)
+    U, psi = fields(11, dims)
+    for prec, link, tdt in ((P.F64, 18, torch.complex128), (P.F32, 12, torch.complex64),
+                            (P.F16, 12, torch.complex128)):
+        Uf = P.pack_gauge(lat, dev(U).to(tdt), prec, link)
+        xo = P.pack_spinor(lat, dev(psi).to(tdt), prec, P.ODD)
+        xe = P.pack_spinor(lat, dev(psi).to(tdt), prec, P.EVEN)
+        ye = P.new_spinor(lat, prec, P.EVEN)
+        yo = P.new_spinor(lat, prec, P.ODD)
+        tmp = P.new_spinor(lat, prec, P.ODD)
+        me = P.new_spinor(lat, prec, P.EVEN)
+
+        def step():
+            P.meo(ye, xo, Uf, -KAPPA, 1.0, xe)
+            P.moe(yo, xe, Uf, dagger=True)
+            P.mhat(me, xe, tmp, Uf, KAPPA)
+
+        step()
+        torch.cuda.synchronize()
+        want = [t.buf.clone() for t in (ye, yo, me)]
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            step()
+        for _ in range(3):
+            for t in (ye, yo, me):
+                t.buf.zero_()
+            P.dslash(P.new_spinor(lat, prec, P.FULL), P.pack_spinor(lat, dev(psi).to(tdt), prec),
+                     Uf)  # unrelated eager work between replays
+            torch.cuda.synchronize()
+            g.replay()
+            torch.cuda.synchronize()
+            for t, w in zip((ye, yo, me), want):
+                assert torch.equal(t.buf, w)
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("dims", [(32, 32, 32, 32), (48, 48, 48, 96)])
+@pytest.mark.parametrize("prec,link", [(P.F64, 18), (P.F64, 12), (P.F32, 12), (P.F32, 18), (P.F16, 12)])
+def test_full_size_sampled(dims, prec, link):
+    """Full-size even-odd hops (the launch shapes and traversal orders the
+    benchmark times) against the oracle evaluated site by site at 256
+    sampled output sites, including every boundary corner of each parity."""
+    from tests.gpu_helpers import DeviceGather
+    lat = P.Lattice(dims)
+    Ud, psid = LI.workload_fields_device(2, dims, "cuda")
+    tdt = torch.complex64 if prec == P.F32 else torch.complex128
+    if prec == P.F32:
+        Ur, pr = Ud.to(tdt).to(torch.complex128), psid.to(tdt).to(torch.complex128)
+        tol = TOL32
+    elif prec == P.F16:
+        Ur, pr, tol = Ud, psid, 5e-3  # against unrounded inputs: storage error only
+    else:
+        Ur, pr, tol = Ud, psid, TOL64
+    Uf = P.pack_gauge(lat, Ud.to(tdt), prec, link)
+    rng = np.random.default_rng(11)
+    for out_par, fn in ((P.EVEN, P.meo), (P.ODD, P.moe)):
+        inp = P.pack_spinor(lat, psid.to(tdt), prec, 1 - out_par)
+        out = P.new_spinor(lat, prec, out_par)
+        mask = torch.from_numpy(LI.parity_mask(dims)).cuda()
+        src = pr.clone()
+        src[mask if out_par == P.ODD else ~mask] = 0
+        for dag in (False, True):
+            fn(out, inp, Uf, dagger=dag)
+            res = P.unpack_spinor(out)
+            sites = np.stack([rng.integers(0, d, 1024) for d in dims], 1)
+            corners = np.array([[x, y, z, t] for x in (0, dims[0] - 1) for y in (0, dims[1] - 1)
+                                for z in (0, dims[2] - 1) for t in (0, dims[3] - 1)])
+            sites = np.concatenate([corners, sites])
+            sites = sites[sites.sum(1) % 2 == out_par][:256]
+            want = dirac.dhop_at(DeviceGather(src), DeviceGather(Ur), sites, dagger=dag)
+            got = res[sites[:, 3], sites[:, 2], sites[:, 1], sites[:, 0]].cpu().numpy()
+            assert rel(got, want) < tol
