@@ -105,6 +105,13 @@ def main():
     ap.add_argument("--no-cg", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cg-lattice", default="32,32,32,32")
+    ap.add_argument("--no-solve-force", action="store_true")
+    ap.add_argument("--solve-force-lattice", default="48,48,48,96")
+    ap.add_argument("--library", default=None,
+                    help="load this liblqcd.so instead of the in-tree one (ablation builds "
+                         "from python -m paper_2001_07557_amd.build -D ... --out DIR)")
+    ap.add_argument("--reductions", action="store_true",
+                    help="only time <a,b> and |a|^2 on the lattice and count distinct results")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB 5 times (counter calibration)")
     args = ap.parse_args()
@@ -129,7 +136,14 @@ def main():
     import torch
 
     import lattice_inputs as LI
+    from paper_2001_07557_amd import _lib
+    if args.library:
+        _lib.LIB_PATH = os.path.abspath(args.library)
     import paper_2001_07557_amd as P
+
+    if args.reductions:
+        print(json.dumps(run_reductions(P, LI, torch, tuple(int(v) for v in args.lattice.split(",")))))
+        return
 
     prec_of = {"f64": P.F64, "f32": P.F32, "f16": P.F16}
     # the solver section runs first; it also brings the GPU to its working clocks
@@ -137,6 +151,11 @@ def main():
     if not args.no_cg:
         cg = run_cg(P, LI, torch, tuple(int(v) for v in args.cg_lattice.split(",")),
                     torch.device("cuda:0"))
+        torch.cuda.empty_cache()
+    solve_force = None
+    if not args.no_solve_force:
+        solve_force = run_solve_force(P, LI, torch, tuple(
+            int(v) for v in args.solve_force_lattice.split(",")), torch.device("cuda:0"))
         torch.cuda.empty_cache()
     lattice = tuple(int(v) for v in args.lattice.split(","))
     lat = P.Lattice(lattice)
@@ -236,6 +255,8 @@ def main():
     }
     if cg is not None:
         line["cg"] = cg
+    if solve_force is not None:
+        line["solve_force"] = solve_force
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(lattice)
     print(json.dumps(line), flush=True)
@@ -272,6 +293,67 @@ def run_cg(P, LI, torch, dims, dev):
             torch.linalg.vector_norm(sols[name] - ref) / torch.linalg.vector_norm(ref))
     out["speedup_f32_vs_f64"] = round(out["f64"]["seconds"] / out["f32-12"]["seconds"], 3)
     out["speedup_f16_vs_f64"] = round(out["f64"]["seconds"] / out["f16-12"]["seconds"], 3)
+    return out
+
+
+def run_reductions(P, LI, torch, dims, calls=50):
+    """<a, b> and |a|^2 on an even half field: time per call (each call
+    synchronises) and the number of distinct results over repeated calls."""
+    lat = P.Lattice(dims)
+    _, psi = LI.workload_fields_device(0, dims, "cuda")
+    out = {"lattice": list(dims), "calls": calls}
+    for name, prec, tdt in (("f64", P.F64, torch.complex128), ("f32", P.F32, torch.complex64)):
+        a = P.pack_spinor(lat, psi.to(tdt), prec, P.EVEN)
+        b = P.pack_spinor(lat, (psi * 0.5 + 0.1).to(tdt), prec, P.EVEN)
+        P.dot(a, b)
+        t0 = time.perf_counter()
+        d = [P.dot(a, b) for _ in range(calls)]
+        t1 = time.perf_counter()
+        n = [P.norm2(a) for _ in range(calls)]
+        t2 = time.perf_counter()
+        out[name] = {"dot_us_per_call": round((t1 - t0) / calls * 1e6, 1),
+                     "norm2_us_per_call": round((t2 - t1) / calls * 1e6, 1),
+                     "dot_distinct": len(set(d)), "norm2_distinct": len(set(n))}
+    return out
+
+
+def run_solve_force(P, LI, torch, dims, dev, kappa=0.1245):
+    """48^3x96 pseudofermion solve plus force, FP32 12-real smoothed links."""
+    lat = P.Lattice(dims)
+    Ud, psid = LI.workload_fields_device(5, dims, dev)
+    t0 = time.perf_counter()
+    Ud = LI.ape_smooth(Ud, steps=10, alpha=0.5).to(torch.complex64)
+    torch.cuda.synchronize()
+    t_ape = time.perf_counter() - t0
+    U_lo = P.pack_gauge(lat, Ud, P.F32, 12)
+    U_hi = P.pack_gauge(lat, Ud, P.F64, 12)  # the FP32 link values, promoted
+    b = P.pack_spinor(lat, psid, P.F64, P.EVEN)
+    del Ud, psid
+    torch.cuda.empty_cache()
+    torch.cuda.synchronize()
+    base = torch.cuda.memory_allocated()
+    torch.cuda.reset_peak_memory_stats()
+    events = []
+    F, st, x, X, Y = P.solve_and_force(b, U_hi, U_lo, kappa, tol=1e-10, events=events)
+    torch.cuda.synchronize()
+    ev = dict(events)
+    ms = {k: ev["start"].elapsed_time(ev[k]) for k in ("solve", "recompute", "force")}
+    v = lat.volume
+    force_ms = ms["force"] - ms["recompute"]
+    force_bytes = v * (4 * 48 + 96 + 96 + 4 * 72)  # links, X, Y read once; F written
+    out = {
+        "lattice": list(dims), "kappa": kappa, "links": "APE-smoothed, FP32 12-real",
+        "solve_seconds": round(ms["solve"] / 1e3, 4), "iterations": st.iterations,
+        "reliable_updates": st.reliable_updates, "true_residual": st.true_residual,
+        "recompute_ms": round(ms["recompute"] - ms["solve"], 3),
+        "force_ms": round(force_ms, 3),
+        "force_gbs": round(force_bytes / (force_ms * 1e-3) / 1e9, 1),
+        "total_seconds": round(ms["force"] / 1e3, 4),
+        "device_gb": {"fields": round(base / 2 ** 30, 2),
+                      "peak_during_solve_and_force": round(torch.cuda.max_memory_allocated() / 2 ** 30, 2)},
+        "smoothing_seconds_untimed": round(t_ape, 2),
+    }
+    del F, x, X, Y, U_lo, U_hi, b
     return out
 
 

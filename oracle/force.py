@@ -94,3 +94,41 @@ def pseudofermion_force(x_e, U, kappa, bc=dirac.DEFAULT_BC):
     """su(3) force of the pseudofermion action given its solution X_e."""
     X, Y = pseudofermion_fields(x_e, U, kappa, bc)
     return su3_force(link_gradient(X, Y, U, 2.0 * kappa ** 2, bc), U)
+
+
+def link_gradient_at(X, Y, U, c0, links, bc=dirac.DEFAULT_BC) -> np.ndarray:
+    """G_mu(x) for a list of links given as rows (x, y, z, t, mu); [n][3][3].
+
+    Same definition as :func:`link_gradient`, evaluated link by link from
+    the fields at x and x + mu (for fields too large to shift whole).
+    """
+    dims = dirac.dims_of(X)
+    links = np.asarray(links, dtype=np.int64)
+    n = links.shape[0]
+    out = np.zeros((n, 3, 3), dtype=np.complex128)
+
+    def at(field, c):
+        return field[c[:, 3], c[:, 2], c[:, 1], c[:, 0]]
+
+    sites = links[:, :4]
+    for mu in range(4):
+        sel = np.nonzero(links[:, 4] == mu)[0]
+        if sel.size == 0:
+            continue
+        here = sites[sel]
+        up = here.copy()
+        up[:, mu] = (here[:, mu] + 1) % dims[mu]
+        sgn = np.where(here[:, mu] == dims[mu] - 1, float(bc[mu]), 1.0)
+        x_h, y_h, x_u, y_u = at(X, here), at(Y, here), at(X, up), at(Y, up)
+        pm = dirac.ONE4 - dirac.GAMMA[mu]
+        pp = dirac.ONE4 + dirac.GAMMA[mu]
+        t1 = np.einsum("nsi,nsj->nij", x_u, np.conj(np.einsum("st,ntc->nsc", pm, y_h)))
+        t2 = np.einsum("nsi,nsj->nij", np.einsum("st,ntc->nsc", pp, y_u), np.conj(x_h))
+        w = c0 * sgn[:, None, None] * (t1 + t2)
+        out[sel] = np.conj(np.swapaxes(w, -1, -2))
+    return out
+
+
+def su3_force_at(G, U_links) -> np.ndarray:
+    """TA(G U^dag) for gathered links ([n][3][3] each)."""
+    return traceless_antihermitian(G @ dirac.dagger3(U_links))

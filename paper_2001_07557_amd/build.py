@@ -77,4 +77,15 @@ def build(verbose: bool = False, jobs: int = 8, defines=(), lib_path: str = LIB,
 
 
 if __name__ == "__main__":
-    print(build(verbose=True))
+    import argparse
+    ap = argparse.ArgumentParser(description="build liblqcd.so for gfx950")
+    ap.add_argument("-D", dest="defines", action="append", default=[],
+                    help="NAME=VALUE kernel option (ablation builds)")
+    ap.add_argument("--out", default=None, help="directory for an ablation build "
+                    "(default: the in-tree library)")
+    a = ap.parse_args()
+    if a.out:
+        print(build(verbose=True, defines=a.defines, lib_path=os.path.join(a.out, "liblqcd.so"),
+                    out_dir=os.path.join(a.out, "obj")))
+    else:
+        print(build(verbose=True, defines=a.defines))

@@ -11,6 +11,13 @@ namespace lqcd {
 
 constexpr int RED_BLOCK = 256;
 
+// Ablation switch: 1 replaces the wave64 -> block -> fixed-order grid
+// reduction by one FP64 atomic add per thread into the result (which is then
+// order-dependent, i.e. not reproducible bit for bit).
+#ifndef LQCD_REDUCE_ATOMIC
+#define LQCD_REDUCE_ATOMIC 0
+#endif
+
 int64_t reduce_blocks(const Geom &g, int nhalf) { return (g.vh * nhalf + RED_BLOCK - 1) / RED_BLOCK; }
 
 template <int P, bool DOT>
@@ -41,11 +48,16 @@ __global__ __launch_bounds__(RED_BLOCK) void reduce_k(const char *a, const char 
         acc[0] = (double)re;
         acc[1] = (double)im;
     }
+#if LQCD_REDUCE_ATOMIC
+    atomicAdd(partial, acc[0]);
+    atomicAdd(partial + 1, acc[1]);
+#else
     block_sum<2>(acc);
     if (threadIdx.x == 0) {
         partial[2 * blockIdx.x] = acc[0];
         partial[2 * blockIdx.x + 1] = acc[1];
     }
+#endif
 }
 
 // Fixed-order sum of n partial records of NV doubles into out[0..NV).
@@ -169,8 +181,18 @@ static int reduce_entry(const lqcd_geom_t *gg, int subset, const void *a, const 
     double *partial = (double *)ws;
     const int64_t nb = reduce_blocks(g, nh);
     double *out = partial + 2 * nb;
+#if LQCD_REDUCE_ATOMIC
+    out = partial;
+    hipError_t ez = hipMemsetAsync(out, 0, 2 * sizeof(double), st);
+    if (ez != hipSuccess) {
+        set_hip_error(ez);
+        return LQCD_EHIP;
+    }
+    launch_reduce(g, nh, (const char *)a, (const char *)b, prec, partial, st);
+#else
     launch_reduce(g, nh, (const char *)a, (const char *)b, prec, partial, st);
     launch_finalize(partial, nb, 2, out, st);
+#endif
     int rc = check_launch();
     if (rc) return rc;
     double host[2];

@@ -193,18 +193,21 @@ static void launch_l(const HopArgs &a, bool dag, bool hasy, bool norm, dim3 grid
     else launch_p<P, LK, false>(a, hasy, norm, grid, st);
 }
 
-// Brick height for the blocked traversal: the largest bz dividing Lz with
-// three t-slices of a brick of input spinors within the L2 budget (0 = plain
-// order).  Needs whole tiles per (z,t) plane.  Measured: the blocked order
-// pays off for FP64, whose input slices overflow an XCD's L2; FP32 and
-// binary16 re-reads are served well enough by the 256 MB Infinity Cache that
-// the plain order is as fast or faster.
+// Brick height for the blocked traversal (0 = plain order); needs whole
+// tiles per (z,t) plane.  See the rules next to LQCD_BRICK_MODE.
 static int brick_height(const Geom &g, int prec, int *plane_tiles) {
     *plane_tiles = 0;
-    if (!LQCD_HOP_BRICK || prec != LQCD_F64) return 0;
+    if (!LQCD_HOP_BRICK || !((LQCD_BRICK_PRECS >> prec) & 1)) return 0;
+    // small lattices live in the caches anyway, and there the extra index
+    // arithmetic and the loss of plain order cost more (16^4 FP32: 48% -> 40%)
+    if (g.vh < ((int64_t)1 << 18)) return 0;
     const int64_t plane = (int64_t)g.lxh * g.L[1];
     if (plane % TILE != 0 || g.vh % TILE != 0) return 0;
     const int64_t pt = plane / TILE;
+    if (LQCD_BRICK_MODE == 1 && g.L[2] % 8 == 0 && g.L[2] > 8) {
+        *plane_tiles = (int)pt;
+        return g.L[2] / 8;
+    }
     const int64_t slice_bytes = pt * spinor_tile_bytes(prec);
     for (int bz = g.L[2] - 1; bz >= 1; --bz) {
         if (g.L[2] % bz == 0 && 3 * bz * slice_bytes <= BRICK_L2_BUDGET) {

@@ -1,5 +1,5 @@
 // Link derivative of c0 Re(Y^dag D_hop X): for every link U_mu(x) (owner
-// computes, one thread per site looping over mu, no atomics)
+// computes: one thread per link, no atomics)
 //   W = c0 s+_mu(x) [ X(x+mu) (x) ((1-g_mu) Y(x))^dag + ((1+g_mu) Y(x+mu)) (x) X(x)^dag ].
 // Because (1 -+ g_mu)/2 is a rank-two hermitian projector, each spin sum
 // reduces to two colour outer products of projected half-spinors:
@@ -114,17 +114,23 @@ __device__ __forceinline__ void force_direction(const ForceArgs &a, int p, int64
     store_link<P, 18>(a.F, g.ntiles, p, s, MU, out);
 }
 
+// One 64-site tile per block; wave w computes the link of direction w for
+// every site of the tile (each link is owned by exactly one thread).
 template <int P, int LK>
 __global__ __launch_bounds__(256) void force_k(ForceArgs a) {
+    const int lane = threadIdx.x & 63;
+    const int w = threadIdx.x >> 6;
     const int64_t blk = xcd_block(blockIdx.x, gridDim.x);
     const int p = blk >= a.bpp ? 1 : 0;
-    const int64_t s = (blk - p * a.bpp) * blockDim.x + threadIdx.x;
+    const int64_t s = (blk - p * a.bpp) * 64 + lane;
     if (s >= a.g.vh) return;
     const Coord c = cb_coords(a.g, p, s);
-    force_direction<0, P, LK>(a, p, s, c);
-    force_direction<1, P, LK>(a, p, s, c);
-    force_direction<2, P, LK>(a, p, s, c);
-    force_direction<3, P, LK>(a, p, s, c);
+    switch (w) {
+        case 0: force_direction<0, P, LK>(a, p, s, c); break;
+        case 1: force_direction<1, P, LK>(a, p, s, c); break;
+        case 2: force_direction<2, P, LK>(a, p, s, c); break;
+        default: force_direction<3, P, LK>(a, p, s, c); break;
+    }
 }
 
 }  // namespace lqcd
@@ -152,9 +158,8 @@ extern "C" int lqcd_fermion_force(const lqcd_geom_t *gg, void *F_out, const void
     a.coeff = coeff;
     a.mode = mode;
     a.accumulate = accumulate ? 1 : 0;
-    const int bs = 128;
-    a.bpp = (g.vh + bs - 1) / bs;
-    dim3 grid((unsigned)(2 * a.bpp)), block(bs);
+    a.bpp = (g.vh + 63) / 64;
+    dim3 grid((unsigned)(2 * a.bpp)), block(256);
     hipStream_t st = (hipStream_t)stream;
     if (prec == LQCD_F64) {
         if (link == 18) force_k<LQCD_F64, 18><<<grid, block, 0, st>>>(a);

@@ -114,6 +114,24 @@ typedef float v2f __attribute__((ext_vector_type(2)));
 typedef uint32_t v4u __attribute__((ext_vector_type(4)));
 typedef uint32_t v2u __attribute__((ext_vector_type(2)));
 
+// Ablation switch: 1 stores FP64/FP32 fields site-major as arrays of complex
+// {re, im} pairs (the layout of the paper's CPU/VE kernels) instead of the
+// 64-site tiles; buffer sizes are identical.  binary16 always uses tiles.
+#ifndef LQCD_LAYOUT_AOS
+#define LQCD_LAYOUT_AOS 0
+#endif
+
+// Links are streamed once per application: load them with the non-temporal
+// hint (ablation switch).
+#ifndef LQCD_LINK_NT
+#define LQCD_LINK_NT 1
+#endif
+template <typename V>
+__device__ __forceinline__ V stream_load(const V *p) {
+    if constexpr (LQCD_LINK_NT) return __builtin_nontemporal_load(p);
+    else return *p;
+}
+
 template <int P> struct real_of { using type = float; };
 template <> struct real_of<LQCD_F64> { using type = double; };
 
@@ -127,7 +145,15 @@ __device__ __forceinline__ void load_spinor(const char *__restrict__ base, int64
     const int64_t tile = s >> TILE_SHIFT;
     const int lane = (int)(s & (TILE - 1));
     const char *t = base + tile * spinor_tile_bytes(P);
-    if constexpr (P == LQCD_F64) {
+    if constexpr (LQCD_LAYOUT_AOS && P == LQCD_F64) {
+        const v2d *w = reinterpret_cast<const v2d *>(base + s * 192);
+#pragma unroll
+        for (int k = 0; k < 12; ++k) v[k] = {w[k].x, w[k].y};
+    } else if constexpr (LQCD_LAYOUT_AOS && P == LQCD_F32) {
+        const v2f *w = reinterpret_cast<const v2f *>(base + s * 96);
+#pragma unroll
+        for (int k = 0; k < 12; ++k) v[k] = {w[k].x, w[k].y};
+    } else if constexpr (P == LQCD_F64) {
         const v2d *w = reinterpret_cast<const v2d *>(t) + lane;
 #pragma unroll
         for (int k = 0; k < 12; ++k) {
@@ -194,7 +220,15 @@ __device__ __forceinline__ void store_spinor(char *__restrict__ base, int64_t s,
     const int64_t tile = s >> TILE_SHIFT;
     const int lane = (int)(s & (TILE - 1));
     char *t = base + tile * spinor_tile_bytes(P);
-    if constexpr (P == LQCD_F64) {
+    if constexpr (LQCD_LAYOUT_AOS && P == LQCD_F64) {
+        v2d *w = reinterpret_cast<v2d *>(base + s * 192);
+#pragma unroll
+        for (int k = 0; k < 12; ++k) w[k] = v2d{v[k].re, v[k].im};
+    } else if constexpr (LQCD_LAYOUT_AOS && P == LQCD_F32) {
+        v2f *w = reinterpret_cast<v2f *>(base + s * 96);
+#pragma unroll
+        for (int k = 0; k < 12; ++k) w[k] = v2f{v[k].re, v[k].im};
+    } else if constexpr (P == LQCD_F64) {
         v2d *w = reinterpret_cast<v2d *>(t) + lane;
 #pragma unroll
         for (int k = 0; k < 12; ++k) w[k * TILE] = v2d{v[k].re, v[k].im};
@@ -249,12 +283,27 @@ __device__ __forceinline__ void load_link(const char *__restrict__ U, int64_t nt
                                           cplx<typename real_of<P>::type> u[9]) {
     const int lane = (int)(s & (TILE - 1));
     const char *t = link_tile<P, LK>(U, ntiles, p, s >> TILE_SHIFT, mu);
-    if constexpr (P == LQCD_F64) {
+    if constexpr (LQCD_LAYOUT_AOS && P != LQCD_F16) {
+        // site-major: [parity][site][mu][complex]
+        constexpr int n = LK == 18 ? 9 : 6;
+        using T = typename real_of<P>::type;
+        const char *l = U + (((int64_t)p * ntiles * TILE + s) * 4 + mu) * (int64_t)(n * 2 * sizeof(T));
+#pragma unroll
+        for (int k = 0; k < n; ++k) {
+            if constexpr (P == LQCD_F64) {
+                v2d d = stream_load(reinterpret_cast<const v2d *>(l) + k);
+                u[k] = {d.x, d.y};
+            } else {
+                v2f d = stream_load(reinterpret_cast<const v2f *>(l) + k);
+                u[k] = {d.x, d.y};
+            }
+        }
+    } else if constexpr (P == LQCD_F64) {
         const v2d *w = reinterpret_cast<const v2d *>(t) + lane;
         constexpr int n = LK == 18 ? 9 : 6;
 #pragma unroll
         for (int k = 0; k < n; ++k) {
-            v2d d = __builtin_nontemporal_load(&w[k * TILE]);
+            v2d d = stream_load(&w[k * TILE]);
             u[k] = {d.x, d.y};
         }
     } else if constexpr (P == LQCD_F32) {
@@ -262,20 +311,20 @@ __device__ __forceinline__ void load_link(const char *__restrict__ U, int64_t nt
         constexpr int n4 = LK == 18 ? 4 : 3;
 #pragma unroll
         for (int k = 0; k < n4; ++k) {
-            v4f f = __builtin_nontemporal_load(&w[k * TILE]);
+            v4f f = stream_load(&w[k * TILE]);
             u[2 * k] = {f.x, f.y};
             u[2 * k + 1] = {f.z, f.w};
         }
         if constexpr (LK == 18) {
             const v2f *w2 = reinterpret_cast<const v2f *>(t + 4 * TILE * WORD) + lane;
-            v2f f = __builtin_nontemporal_load(w2);
+            v2f f = stream_load(w2);
             u[8] = {f.x, f.y};
         }
     } else {
         const v4u *w = reinterpret_cast<const v4u *>(t) + lane;
-        v4u q = __builtin_nontemporal_load(w);
+        v4u q = stream_load(w);
         const v2u *w2 = reinterpret_cast<const v2u *>(t + TILE * WORD) + lane;
-        v2u q2 = __builtin_nontemporal_load(w2);
+        v2u q2 = stream_load(w2);
         uint32_t a[6] = {q.x, q.y, q.z, q.w, q2.x, q2.y};
 #pragma unroll
         for (int j = 0; j < 6; ++j) {
@@ -294,7 +343,16 @@ __device__ __forceinline__ void store_link(char *__restrict__ U, int64_t ntiles,
                                            const cplx<typename real_of<P>::type> u[9]) {
     const int lane = (int)(s & (TILE - 1));
     char *t = const_cast<char *>(link_tile<P, LK>(U, ntiles, p, s >> TILE_SHIFT, mu));
-    if constexpr (P == LQCD_F64) {
+    if constexpr (LQCD_LAYOUT_AOS && P != LQCD_F16) {
+        constexpr int n = LK == 18 ? 9 : 6;
+        using T = typename real_of<P>::type;
+        char *l = U + (((int64_t)p * ntiles * TILE + s) * 4 + mu) * (int64_t)(n * 2 * sizeof(T));
+#pragma unroll
+        for (int k = 0; k < n; ++k) {
+            if constexpr (P == LQCD_F64) reinterpret_cast<v2d *>(l)[k] = v2d{u[k].re, u[k].im};
+            else reinterpret_cast<v2f *>(l)[k] = v2f{u[k].re, u[k].im};
+        }
+    } else if constexpr (P == LQCD_F64) {
         v2d *w = reinterpret_cast<v2d *>(t) + lane;
         constexpr int n = LK == 18 ? 9 : 6;
 #pragma unroll

@@ -119,6 +119,13 @@ class SpinorField:
     def ptr(self) -> int:
         return self.buf.data_ptr()
 
+    def half(self, parity: int) -> "SpinorField":
+        """View of the even or odd half of a full field (shares memory)."""
+        if self.subset != FULL:
+            raise RuntimeError("half() needs a full field")
+        hb = self.lattice.spinor_bytes(self.prec, EVEN)
+        return SpinorField(self.lattice, self.prec, parity, self.buf[parity * hb:(parity + 1) * hb])
+
 
 @dataclass
 class GaugeField:
@@ -346,3 +353,52 @@ def fermion_force(X: SpinorField, Y: SpinorField, U: GaugeField, coeff: float, m
                                           int(accumulate), U.prec, U.link, _stream()),
            "fermion_force")
     return out
+
+
+def solve_and_force(phi_e: SpinorField, U_hi: GaugeField, U_lo: GaugeField, kappa: float,
+                    tol: float = 1e-10, maxiter: int = 20000, reliable_every: int = 100,
+                    U_force: Optional[GaugeField] = None, events: Optional[list] = None):
+    """Pseudofermion solve plus force for S = phi_e^dag (Mhat^dag Mhat)^-1 phi_e.
+
+    1. X_e = (Mhat^dag Mhat)^-1 phi_e by mixed-precision CG (FP64 result);
+    2. X_o = D_oe X_e, Y_e = Mhat X_e, Y_o = (D_eo)^dag Y_e recomputed by hop
+       kernels in the force precision (nothing from the solve is kept but X_e);
+    3. F = TA(G U^dag) with G the link derivative of 2 kappa^2 Re(Y^dag dD_hop X).
+    U_force (default U_lo; an FP32 field when U_lo is binary16) sets the
+    precision of steps 2-3.  Returns (F, cg stats, X_e, X, Y).  With
+    `events` a list, (stage name, torch.cuda.Event) pairs are appended at the
+    start and after each stage, on the current stream.
+    """
+
+    def mark(name):
+        if events is not None:
+            e = torch.cuda.Event(enable_timing=True)
+            e.record()
+            events.append((name, e))
+
+    mark("start")
+    lat = phi_e.lattice
+    Uf = U_force if U_force is not None else U_lo
+    if Uf.prec == F16:
+        raise RuntimeError("the force runs in FP64 or FP32: pass an FP32 U_force")
+    x = new_spinor(lat, F64, EVEN, phi_e.buf.device)
+    stats = cg_solve(x, phi_e, U_hi, U_lo, kappa, tol=tol, maxiter=maxiter,
+                     reliable_every=reliable_every)
+    mark("solve")
+    fp = Uf.prec
+    X = new_spinor(lat, fp, FULL, x.buf.device)
+    Y = new_spinor(lat, fp, FULL, x.buf.device)
+    Xe, Xo, Ye, Yo = X.half(EVEN), X.half(ODD), Y.half(EVEN), Y.half(ODD)
+    if fp == F64:
+        axpby(1.0, x, 0.0, Xe)
+    else:
+        convert(Xe, x)
+    moe(Xo, Xe, Uf)
+    tmp = new_spinor(lat, fp, ODD, x.buf.device)
+    mhat(Ye, Xe, tmp, Uf, kappa)
+    moe(Yo, Ye, Uf, dagger=True)
+    del tmp
+    mark("recompute")
+    F = fermion_force(X, Y, Uf, 2.0 * kappa * kappa, mode=0)
+    mark("force")
+    return F, stats, x, X, Y

@@ -183,21 +183,52 @@ def test_pseudofermion_force_pipeline_small():
     U_hi = P.pack_gauge(lat, dev(U), P.F64, 18)
     U_lo = P.pack_gauge(lat, dev(U).to(torch.complex64), P.F32, 12)
     b = P.pack_spinor(lat, dev(phi), P.F64, P.EVEN)
-    x = P.new_spinor(lat, P.F64, P.EVEN)
-    st = P.cg_solve(x, b, U_hi, U_lo, KAPPA, tol=1e-12)
-    assert st.iterations < 200, st
+    F, st, x, _, _ = P.solve_and_force(b, U_hi, U_lo, KAPPA, tol=1e-12, U_force=U_hi)
+    assert st.status == 0 and st.iterations < 200, st
     x_e = host(P.unpack_spinor(x))
-    # recompute X_o = D_oe X_e, Y_e = Mhat X_e, Y_o = (D_eo)^dag Y_e on the GPU
-    Xf = P.new_spinor(lat, P.F64, P.FULL)
-    Yf = P.new_spinor(lat, P.F64, P.FULL)
-    hb = lat.spinor_bytes(P.F64, P.EVEN)
-    half = lambda f, par: P.SpinorField(lat, P.F64, par, f.buf[par * hb:(par + 1) * hb])  # noqa: E731
-    P.convert(half(Xf, P.EVEN), x)
-    P.moe(half(Xf, P.ODD), x, U_hi)
-    tmp = P.new_spinor(lat, P.F64, P.ODD)
-    P.mhat(half(Yf, P.EVEN), x, tmp, U_hi, KAPPA)
-    P.moe(half(Yf, P.ODD), half(Yf, P.EVEN), U_hi, dagger=True)
-    F = host(P.unpack_gauge(P.fermion_force(Xf, Yf, U_hi, 2 * KAPPA ** 2, mode=0)))
     want = force.pseudofermion_force(x_e, U, KAPPA)
-    assert rel(F, want) < 1e-12
-    assert solver.true_residual(x_e, dirac.project(phi, 0), U, KAPPA) <= 1e-12
+    assert rel(host(P.unpack_gauge(F)), want) < 1e-12
+    assert solver.true_residual(x_e, dirac.project(phi, 0), U, KAPPA) <= 1.0001e-12
+
+
+@pytest.mark.slow
+def test_solve_and_force_48x3x96():
+    """The 48^3x96 solve-plus-force workload: FP32 12-real smoothed links
+    (kappa 0.1245), mixed CG to 1e-10, recomputed X_o, Y_e, Y_o, FP32 force.
+    The residual is recomputed in FP64 through the operator entry points and
+    the force is checked against the oracle's link formula at 128 sampled
+    links (FP64 arithmetic on the same stored X, Y and links)."""
+    from tests.gpu_helpers import DeviceGather
+    dims = (48, 48, 48, 96)
+    kappa = 0.1245
+    lat = P.Lattice(dims)
+    Ud, psid = LI.workload_fields_device(5, dims, "cuda")
+    Ud = LI.ape_smooth(Ud, steps=10, alpha=0.5).to(torch.complex64)
+    U_lo = P.pack_gauge(lat, Ud, P.F32, 12)
+    U_hi = P.pack_gauge(lat, Ud, P.F64, 12)  # the FP32 values, promoted
+    b = P.pack_spinor(lat, psid, P.F64, P.EVEN)
+    del psid
+    F, st, x, X, Y = P.solve_and_force(b, U_hi, U_lo, kappa, tol=1e-10)
+    assert st.status == 0 and st.true_residual <= 1e-10
+    t1 = P.new_spinor(lat, P.F64, P.EVEN)
+    t2 = P.new_spinor(lat, P.F64, P.EVEN)
+    tmp = P.new_spinor(lat, P.F64, P.ODD)
+    P.mhat(t1, x, tmp, U_hi, kappa)
+    P.mhat(t2, t1, tmp, U_hi, kappa, dagger=True)
+    P.axpby(1.0, b, -1.0, t2)
+    assert np.sqrt(P.norm2(t2) / P.norm2(b)) <= 1.0001e-10
+    del t1, t2, tmp
+    Xc = P.unpack_spinor(X)
+    Yc = P.unpack_spinor(Y)
+    Uc = P.unpack_gauge(U_lo)  # the links the kernels see (row 2 rebuilt)
+    Fc = P.unpack_gauge(F, dtype=torch.complex64)
+    rng = np.random.default_rng(12)
+    links = np.stack([rng.integers(0, d, 128) for d in dims] + [rng.integers(0, 4, 128)], 1)
+    links[0] = [0, 0, 0, dims[3] - 1, 3]
+    links[1] = [dims[0] - 1, dims[1] - 1, dims[2] - 1, dims[3] - 1, 0]
+    G = force.link_gradient_at(DeviceGather(Xc), DeviceGather(Yc), None, 2 * kappa ** 2, links)
+    idx = tuple(torch.as_tensor(links[:, k]) for k in (3, 2, 1, 0, 4))
+    ul = Uc[idx].cpu().numpy()
+    want = force.su3_force_at(G, ul)
+    got = Fc[idx].cpu().numpy().astype(np.complex128)
+    assert rel(got, want) < 2e-6

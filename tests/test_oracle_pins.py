@@ -518,3 +518,22 @@ def test_ape_smoothing_raises_plaquette():
     assert all(b > a for a, b in zip(plaq, plaq[1:]))
     assert LI.unitarity_defect(U.reshape(-1, 3, 3)) < 1e-14
     assert np.abs(LI.det3(U) - 1).max() < 1e-14
+
+
+def test_sampled_link_gradient_matches_field():
+    dims = (4, 6, 2, 8)
+    U, X = LI.workload_fields(18, dims)
+    Y = LI.gaussian_spinor(np.random.default_rng(19), dims)
+    bc = (1, -1, 1, -1)
+    G = force.link_gradient(X, Y, U, 0.7, bc)
+    rng = np.random.default_rng(20)
+    links = np.stack([rng.integers(0, d, 60) for d in dims] + [rng.integers(0, 4, 60)], 1)
+    links[0] = [dims[0] - 1, 0, 0, 0, 0]
+    links[1] = [0, dims[1] - 1, 0, dims[3] - 1, 1]
+    links[2] = [1, 1, 1, dims[3] - 1, 3]
+    got = force.link_gradient_at(X, Y, U, 0.7, links, bc)
+    want = G[links[:, 3], links[:, 2], links[:, 1], links[:, 0], links[:, 4]]
+    assert np.abs(got - want).max() < 1e-13
+    ul = U[links[:, 3], links[:, 2], links[:, 1], links[:, 0], links[:, 4]]
+    F = force.su3_force(G, U)[links[:, 3], links[:, 2], links[:, 1], links[:, 0], links[:, 4]]
+    assert np.abs(force.su3_force_at(got, ul) - F).max() < 1e-13
