@@ -106,6 +106,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cg-lattice", default="32,32,32,32")
     ap.add_argument("--no-solve-force", action="store_true")
+    ap.add_argument("--no-blocks", action="store_true",
+                    help="skip the SU(3)-product / shift / split_rotate throughput section")
+    ap.add_argument("--blocks-lattice", default="32,32,32,32")
     ap.add_argument("--solve-force-lattice", default="48,48,48,96")
     ap.add_argument("--library", default=None,
                     help="load this liblqcd.so instead of the in-tree one (ablation builds "
@@ -156,6 +159,11 @@ def main():
     if not args.no_solve_force:
         solve_force = run_solve_force(P, LI, torch, tuple(
             int(v) for v in args.solve_force_lattice.split(",")), torch.device("cuda:0"))
+        torch.cuda.empty_cache()
+    copy_gbs = measure_copy(torch)
+    blocks = None
+    if not args.no_blocks:
+        blocks = run_blocks(P, LI, torch, tuple(int(v) for v in args.blocks_lattice.split(",")))
         torch.cuda.empty_cache()
     lattice = tuple(int(v) for v in args.lattice.split(","))
     lat = P.Lattice(lattice)
@@ -252,11 +260,14 @@ def main():
             "traffic": None if traffic is None else round(traffic / t_launch / 1e9, 1),
         },
         "variants": results,
+        "device_copy_gbs": copy_gbs,
     }
     if cg is not None:
         line["cg"] = cg
     if solve_force is not None:
         line["solve_force"] = solve_force
+    if blocks is not None:
+        line["building_blocks"] = blocks
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(lattice)
     print(json.dumps(line), flush=True)
@@ -293,6 +304,86 @@ def run_cg(P, LI, torch, dims, dev):
             torch.linalg.vector_norm(sols[name] - ref) / torch.linalg.vector_norm(ref))
     out["speedup_f32_vs_f64"] = round(out["f64"]["seconds"] / out["f32-12"]["seconds"], 3)
     out["speedup_f16_vs_f64"] = round(out["f64"]["seconds"] / out["f16-12"]["seconds"], 3)
+    return out
+
+
+def measure_copy(torch, mib=2048, reps=10):
+    """Device-to-device copy bandwidth (read + write bytes / time), the
+    practical ceiling a streaming kernel can reach on this GPU."""
+    a = torch.ones(mib << 20, dtype=torch.uint8, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    t = e0.elapsed_time(e1) * 1e-3 / reps
+    del a, b
+    torch.cuda.empty_cache()
+    return round(2 * (mib << 20) / t / 1e9, 1)
+
+
+def _time_graph(torch, fn, reps=20):
+    """Average time (s) of fn() replayed from a HIP graph, HIP events."""
+    fn()
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        fn()
+    g.replay()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        g.replay()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) * 1e-3 / reps
+
+
+def run_blocks(P, LI, torch, dims):
+    """Throughput of the paper's building blocks on one lattice: the lattice
+    SU(3) product (Fig. 4a-c workload; 3 links of traffic, 198 flop per
+    link), the boundary-aware shift (2 spinors per site) and split_rotate
+    over 64-element FP64 vectors (2 x 8 B per element)."""
+    lat = P.Lattice(dims)
+    Ud, psi = LI.workload_fields_device(8, dims, "cuda")
+    Vd, _ = LI.workload_fields_device(9, dims, "cuda")
+    out = {"lattice": list(dims)}
+    pname = {P.F64: "f64", P.F32: "f32"}
+    link_bytes = {(P.F64, 18): 144, (P.F64, 12): 96, (P.F32, 18): 72, (P.F32, 12): 48}
+    for (prec, link), lb in link_bytes.items():
+        tdt = torch.complex64 if prec == P.F32 else torch.complex128
+        Uf = P.pack_gauge(lat, Ud.to(tdt), prec, link)
+        Vf = P.pack_gauge(lat, Vd.to(tdt), prec, link)
+        Wf = P.new_gauge(lat, prec, link)
+        t = _time_graph(torch, lambda: P.su3_mul(Wf, Uf, Vf))
+        nl = 4 * lat.volume
+        out[f"su3_mul_{pname[prec]}-{link}"] = {
+            "us": round(t * 1e6, 2), "gbs": round(3 * lb * nl / t / 1e9, 1),
+            "frac_hbm": round(3 * lb * nl / t / 1e9 / PEAK_HBM, 4),
+            "gflops": round(198 * nl / t / 1e9, 1)}
+        del Uf, Vf, Wf
+    for prec, sb in ((P.F64, 192), (P.F32, 96)):
+        tdt = torch.complex64 if prec == P.F32 else torch.complex128
+        src = P.pack_spinor(lat, psi.to(tdt), prec)
+        dst = P.new_spinor(lat, prec, P.FULL)
+        t = _time_graph(torch, lambda: P.cshift(dst, src, 3, 1))
+        out[f"cshift_t_{pname[prec]}"] = {
+            "us": round(t * 1e6, 2), "gbs": round(2 * sb * lat.volume / t / 1e9, 1),
+            "frac_hbm": round(2 * sb * lat.volume / t / 1e9 / PEAK_HBM, 4)}
+        del src, dst
+    x = torch.randn(lat.volume * 12, dtype=torch.float64, device="cuda").reshape(-1, 64)
+    y = torch.empty_like(x)
+    t = _time_graph(torch, lambda: P.split_rotate(y, x, 4, 3))
+    out["split_rotate_vl64_s4"] = {"us": round(t * 1e6, 2),
+                                   "gbs": round(2 * x.numel() * 8 / t / 1e9, 1),
+                                   "frac_hbm": round(2 * x.numel() * 8 / t / 1e9 / PEAK_HBM, 4)}
     return out
 
 

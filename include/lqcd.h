@@ -256,6 +256,40 @@ int lqcd_fermion_force(const lqcd_geom_t *g, void *F_out, const void *X, const v
                        const void *U, double coeff, int mode, int accumulate,
                        int prec, int link, void *stream);
 
+/* ---------------------------------------------------------------------- */
+/* shifts and lattice SU(3) products (the paper's building blocks)          */
+/* ---------------------------------------------------------------------- */
+
+/* Shift of a full spinor field: out(x) = s in(x + dir mu_hat), dir = +1 or
+   -1, with s = bc[mu] when the step wraps around the lattice (from the last
+   slice for dir = +1, the first for dir = -1) and 1 otherwise.  The stencil
+   building block of Sec. 3.1 ("shift and stencil operations"); with one site
+   per lane it needs no lane rearrangement.  out must not alias in.  All
+   precisions; binary16 fields are copied exactly (the sign rides on the
+   site scale). */
+int lqcd_cshift(const lqcd_geom_t *g, void *out, const void *in, int mu, int dir, int prec,
+                void *stream);
+
+/* The lane permutation of Sec. 3.1 on nvec consecutive vectors of vl
+   elements of elem_bytes (8: one double or FP32 complex, 16: one FP64
+   complex): every vector is split into s blocks of w = vl/s elements and each
+   block is rotated left by r,  out[v][i] = in[v][(i + r) mod w + (i div w) w].
+   s = 1 is a plain rotation.  (For complex data stored as reals the paper
+   rotates by 2r reals; with elem_bytes = 16 r counts complexes.)  Vectors
+   with vl dividing 64 are permuted in registers inside a wavefront.
+   out must not alias in; EINVAL if s does not divide vl. */
+int lqcd_split_rotate(void *out, const void *in, int64_t nvec, int vl, int s, int r,
+                      int elem_bytes, void *stream);
+
+/* Lattice SU(3) product W_mu(x) = op(U_mu(x)) op(V_mu(x)) for all 4V links,
+   op = hermitian conjugate when adj_u / adj_v != 0: the SU(3) matrix-matrix
+   workload of Sec. 3.3 (Fig. 4a-c).  All three fields share (prec, link),
+   prec F64 or F32; LINK12 inputs are rebuilt to 3x3 and the product is
+   stored by its rows 0 and 1 (SU(3) is closed under products).  W may alias
+   U or V. */
+int lqcd_su3_mul(const lqcd_geom_t *g, void *W, const void *U, const void *V, int adj_u,
+                 int adj_v, int prec, int link, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

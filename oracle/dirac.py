@@ -57,6 +57,16 @@ def shift(field: np.ndarray, mu: int, s: int) -> np.ndarray:
     return np.roll(field, -s, axis=3 - mu)
 
 
+def cshift(field: np.ndarray, mu: int, s: int, bc=DEFAULT_BC) -> np.ndarray:
+    """out(x) = field(x + s mu_hat) times bc_mu when the step crosses the
+    boundary (s = +1 from the last slice, s = -1 from the first)."""
+    dims = dims_of(field)
+    out = shift(field, mu, s)
+    edge = dims[mu] - 1 if s > 0 else 0
+    sign = np.where(coord(dims, mu) == edge, float(bc[mu]), 1.0)
+    return out * sign.reshape(sign.shape + (1,) * (field.ndim - 4))
+
+
 def coord(dims: Sequence[int], mu: int) -> np.ndarray:
     """Array [t][z][y][x] holding the coordinate x_mu of each site."""
     lx, ly, lz, lt = dims

@@ -8,6 +8,6 @@ from .lqcd import (  # noqa: F401
     LQCDError, Lattice, SpinorField, GaugeField, CGStats,
     new_spinor, new_gauge, pack_spinor, unpack_spinor, pack_gauge, unpack_gauge,
     dslash, wilson, meo, moe, mhat, dot, norm2, axpby, convert,
-    cg_workspace, cg_solve, fermion_force, solve_and_force,
+    cg_workspace, cg_solve, fermion_force, solve_and_force, cshift, split_rotate, su3_mul,
 )
 from .autograd import WilsonMatrix, wilson_matrix  # noqa: F401

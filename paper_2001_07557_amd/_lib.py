@@ -74,6 +74,11 @@ SIGNATURES = {
                               ctypes.POINTER(CGStatsT), c_void_p]),
     "lqcd_fermion_force": (c_int, [G, c_void_p, c_void_p, c_void_p, c_void_p, c_double, c_int,
                                    c_int, c_int, c_int, c_void_p]),
+    "lqcd_cshift": (c_int, [G, c_void_p, c_void_p, c_int, c_int, c_int, c_void_p]),
+    "lqcd_split_rotate": (c_int, [c_void_p, c_void_p, ctypes.c_int64, c_int, c_int, c_int, c_int,
+                                  c_void_p]),
+    "lqcd_su3_mul": (c_int, [G, c_void_p, c_void_p, c_void_p, c_int, c_int, c_int, c_int,
+                             c_void_p]),
 }
 
 _lib = None

@@ -402,3 +402,42 @@ def solve_and_force(phi_e: SpinorField, U_hi: GaugeField, U_lo: GaugeField, kapp
     F = fermion_force(X, Y, Uf, 2.0 * kappa * kappa, mode=0)
     mark("force")
     return F, stats, x, X, Y
+
+
+# ----------------------------------------------------------------------------
+# shifts and SU(3) products
+# ----------------------------------------------------------------------------
+
+def cshift(out: SpinorField, inp: SpinorField, mu: int, direction: int) -> SpinorField:
+    """out(x) = bc^[wrap] inp(x + direction mu_hat) on full fields."""
+    _same(out, inp)
+    if out.subset != FULL or inp.subset != FULL:
+        raise RuntimeError("cshift works on full fields")
+    _check(_lib.load().lqcd_cshift(out.lattice.ref(), out.ptr, inp.ptr, mu, direction, out.prec,
+                                   _stream()), "cshift")
+    return out
+
+
+def split_rotate(out: torch.Tensor, inp: torch.Tensor, s: int, r: int) -> torch.Tensor:
+    """Split each row (last axis, length VL) into s blocks and rotate each
+    block left by r elements (float64, complex64 or complex128 tensors)."""
+    if inp.dtype != out.dtype or inp.shape != out.shape:
+        raise RuntimeError("split_rotate needs matching tensors")
+    eb = {torch.float64: 8, torch.complex64: 8, torch.complex128: 16}.get(inp.dtype)
+    if eb is None:
+        raise RuntimeError("split_rotate takes float64, complex64 or complex128")
+    vl = inp.shape[-1]
+    nvec = inp.numel() // vl if vl else 0
+    _check(_lib.load().lqcd_split_rotate(_ptr(out), _ptr(inp), nvec, vl, s, r, eb, _stream()),
+           "split_rotate")
+    return out
+
+
+def su3_mul(W: GaugeField, U: GaugeField, V: GaugeField, adj_u: bool = False,
+            adj_v: bool = False) -> GaugeField:
+    """W = op(U) op(V) on every link."""
+    if not (W.prec == U.prec == V.prec and W.link == U.link == V.link):
+        raise RuntimeError("su3_mul fields share precision and link format")
+    _check(_lib.load().lqcd_su3_mul(W.lattice.ref(), W.ptr, U.ptr, V.ptr, int(adj_u), int(adj_v),
+                                    W.prec, W.link, _stream()), "su3_mul")
+    return W

@@ -537,3 +537,65 @@ def test_sampled_link_gradient_matches_field():
     ul = U[links[:, 3], links[:, 2], links[:, 1], links[:, 0], links[:, 4]]
     F = force.su3_force(G, U)[links[:, 3], links[:, 2], links[:, 1], links[:, 0], links[:, 4]]
     assert np.abs(force.su3_force_at(got, ul) - F).max() < 1e-13
+
+
+# ----------------------------------------------------------------------------
+# shifts, the lane permutation of Sec. 3.1, SU(3) products
+# ----------------------------------------------------------------------------
+
+def test_cshift_is_the_hop_of_the_free_operator():
+    """With unit links, D_hop is the projector-weighted sum of the shifts."""
+    dims = (4, 6, 2, 4)
+    _, psi = LI.workload_fields(21, dims)
+    U = unit_links(dims)
+    want = dirac.dhop(psi, U, BC)
+    got = sum(dirac.spin_mul(ONE4 - GAMMA[m], dirac.cshift(psi, m, 1, BC)) +
+              dirac.spin_mul(ONE4 + GAMMA[m], dirac.cshift(psi, m, -1, BC)) for m in range(4))
+    assert np.abs(got - want).max() < 1e-14
+    # a shift there and back is the identity (sign squared)
+    for m in range(4):
+        assert np.array_equal(dirac.cshift(dirac.cshift(psi, m, 1, BC), m, -1, BC), psi)
+    # L_mu shifts forward multiply by the boundary sign
+    x = psi
+    for _ in range(dims[3]):
+        x = dirac.cshift(x, 3, 1, BC)
+    assert np.array_equal(x, -psi)
+
+
+def test_split_rotate_pins():
+    from oracle.shift import split_rotate
+    rng = np.random.default_rng(22)
+    v = rng.standard_normal((3, 32))
+    # s = 1 is a plain rotation
+    for r in range(5):
+        assert np.array_equal(split_rotate(v, 1, r), np.roll(v, -r, axis=-1))
+    # the definition element by element on one case
+    vl, s, r = 32, 4, 3
+    w = vl // s
+    want = np.array([v[0][(i + r) % w + (i // w) * w] for i in range(vl)])
+    assert np.array_equal(split_rotate(v, s, r)[0], want)
+    # blocks rotate independently; r = w is the identity; rotations compose
+    for s in (1, 2, 4, 8):
+        w = 32 // s
+        assert np.array_equal(split_rotate(v, s, w), v)
+        assert np.array_equal(split_rotate(split_rotate(v, s, 2), s, 3), split_rotate(v, s, 5))
+    # complex data stored as (re, im) pairs rotates by 2 r reals
+    z = rng.standard_normal(16) + 1j * rng.standard_normal(16)
+    reals = z.view(np.float64)
+    assert np.array_equal(split_rotate(reals, 4, 2 * 3).view(np.complex128), split_rotate(z, 4, 3))
+
+
+def test_su3_product_pins():
+    U, _ = LI.workload_fields(23, (2, 2, 2, 2))
+    V, _ = LI.workload_fields(24, (2, 2, 2, 2))
+    W = links.su3_product(U, V)
+    # index sum written out on a few links
+    for idx in [(0, 0, 0, 0, 0), (1, 1, 0, 1, 3), (0, 1, 1, 0, 2)]:
+        u, v = U[idx], V[idx]
+        want = np.array([[sum(u[i, k] * v[k, j] for k in range(3)) for j in range(3)] for i in range(3)])
+        assert np.abs(W[idx] - want).max() < 1e-15
+    # closure in SU(3); U^dag U = 1
+    assert LI.unitarity_defect(W.reshape(-1, 3, 3)) < 1e-14
+    assert np.abs(LI.det3(W) - 1).max() < 1e-14
+    eye = links.su3_product(U, U, adj_u=True)
+    assert np.abs(eye - np.eye(3)).max() < 1e-14
