@@ -43,10 +43,21 @@ HEADLINE = ("f32", 12)
 KAPPA = 0.124
 
 
+# the sources the hop kernels are compiled from
+HOP_SOURCES = ("dslash.hip", "hop_common.h", "lqcd_internal.h", "reduce.h")
+
+
+def log(msg: str) -> None:
+    """Progress on stderr (the JSON line is the only stdout output)."""
+    print(f"bench: {msg}", file=sys.stderr, flush=True)
+
+
 def source_hash() -> str:
+    """Hash of the hop kernels' sources: a counter summary taken for another
+    version of the kernel no longer applies."""
     h = hashlib.sha256()
     d = os.path.join(ROOT, "paper_2001_07557_amd", "csrc")
-    for f in sorted(os.listdir(d)):
+    for f in HOP_SOURCES:
         with open(os.path.join(d, f), "rb") as fh:
             h.update(f.encode() + fh.read())
     return h.hexdigest()[:16]
@@ -155,16 +166,18 @@ def main():
         cg = run_cg(P, LI, torch, tuple(int(v) for v in args.cg_lattice.split(",")),
                     torch.device("cuda:0"))
         torch.cuda.empty_cache()
+        log("solver section done")
     solve_force = None
     if not args.no_solve_force:
         solve_force = run_solve_force(P, LI, torch, tuple(
             int(v) for v in args.solve_force_lattice.split(",")), torch.device("cuda:0"))
         torch.cuda.empty_cache()
-    copy_gbs = measure_copy(torch)
+        log("solve-plus-force section done")
     blocks = None
     if not args.no_blocks:
         blocks = run_blocks(P, LI, torch, tuple(int(v) for v in args.blocks_lattice.split(",")))
         torch.cuda.empty_cache()
+        log("building blocks done")
     lattice = tuple(int(v) for v in args.lattice.split(","))
     lat = P.Lattice(lattice)
     dev = torch.device("cuda:0")
@@ -227,6 +240,7 @@ def main():
             "us_per_launch": round(t_launch * 1e6, 3), "bytes_per_site": BYTES_SITE[var]}
         if var == HEADLINE or args.only:
             headline = (var, ms, t_launch, bytes_launch, gflops, gbs)
+        log(f"{var[0]}-{var[1]}: {gflops:.1f} GFlop/s, {gbs:.1f} GB/s")
         del Uf, odd_in, even_in, even_out, odd_out
     del U, psi
     torch.cuda.empty_cache()
@@ -260,7 +274,6 @@ def main():
             "traffic": None if traffic is None else round(traffic / t_launch / 1e9, 1),
         },
         "variants": results,
-        "device_copy_gbs": copy_gbs,
     }
     if cg is not None:
         line["cg"] = cg
@@ -269,6 +282,7 @@ def main():
     if blocks is not None:
         line["building_blocks"] = blocks
     if not args.no_cpu:
+        log("timing the CPU oracle")
         line["cpu_baseline"] = cpu_baseline(lattice)
     print(json.dumps(line), flush=True)
 
@@ -282,10 +296,14 @@ def run_cg(P, LI, torch, dims, dev):
     b = P.pack_spinor(lat, psid, P.F64, P.EVEN)
     out = {"lattice": list(dims), "kappa": KAPPA, "tol": 1e-10, "links": "APE-smoothed 10 x 0.5"}
     sols = {}
-    for name, (prec, link, rel_every) in {"f64": (P.F64, 18, 0), "f32-12": (P.F32, 12, 100),
+    U_hi12 = P.pack_gauge(lat, Ud, P.F64, 12)
+    for name, (prec, link, rel_every) in {"f64": (P.F64, 18, 0), "f64-12": (P.F64, 12, 0),
+                                          "f32-12": (P.F32, 12, 100),
                                           "f16-12": (P.F16, 12, 100)}.items():
-        U_lo = U_hi if prec == P.F64 else P.pack_gauge(
-            lat, Ud.to(torch.complex64) if prec == P.F32 else Ud, prec, link)
+        if prec == P.F64:
+            U_lo = U_hi if link == 18 else U_hi12
+        else:
+            U_lo = P.pack_gauge(lat, Ud.to(torch.complex64) if prec == P.F32 else Ud, prec, link)
         ws = P.cg_workspace(lat, prec, link, dev)
         x = P.new_spinor(lat, P.F64, P.EVEN)
         P.cg_solve(x, b, U_hi, U_lo, KAPPA, tol=1e-10, maxiter=20000,
@@ -295,36 +313,18 @@ def run_cg(P, LI, torch, dims, dev):
         st = P.cg_solve(x, b, U_hi, U_lo, KAPPA, tol=1e-10, maxiter=20000,
                         reliable_every=rel_every, workspace=ws)
         sols[name] = P.unpack_spinor(x)
+        del U_lo
         out[name] = {"seconds": round(st.seconds, 4), "iterations": st.iterations,
                      "reliable_updates": st.reliable_updates,
                      "true_residual": st.true_residual}
     ref = sols["f64"]
-    for name in ("f32-12", "f16-12"):
+    for name in ("f64-12", "f32-12", "f16-12"):
         out[name]["rel_err_vs_f64_solution"] = float(
             torch.linalg.vector_norm(sols[name] - ref) / torch.linalg.vector_norm(ref))
     out["speedup_f32_vs_f64"] = round(out["f64"]["seconds"] / out["f32-12"]["seconds"], 3)
     out["speedup_f16_vs_f64"] = round(out["f64"]["seconds"] / out["f16-12"]["seconds"], 3)
+    out["speedup_f32_vs_f64_12"] = round(out["f64-12"]["seconds"] / out["f32-12"]["seconds"], 3)
     return out
-
-
-def measure_copy(torch, mib=2048, reps=10):
-    """Device-to-device copy bandwidth (read + write bytes / time), the
-    practical ceiling a streaming kernel can reach on this GPU."""
-    a = torch.ones(mib << 20, dtype=torch.uint8, device="cuda")
-    b = torch.empty_like(a)
-    b.copy_(a)
-    torch.cuda.synchronize()
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    e0.record()
-    for _ in range(reps):
-        b.copy_(a)
-    e1.record()
-    torch.cuda.synchronize()
-    t = e0.elapsed_time(e1) * 1e-3 / reps
-    del a, b
-    torch.cuda.empty_cache()
-    return round(2 * (mib << 20) / t / 1e9, 1)
 
 
 def _time_graph(torch, fn, reps=20):

@@ -221,8 +221,9 @@ size_t lqcd_cg_workspace_bytes(const lqcd_geom_t *g, int inner_prec, int inner_l
  *   A reliable update folds the inner solution into x_e, recomputes the true
  *   residual in FP64 and restarts the inner residual from it, keeping the
  *   search direction; it is taken every `reliable_every` iterations (0 =
- *   never on a schedule), whenever an FP32/F16 inner residual has fallen by
- *   10x since the last update (the inner recurrence is not trusted further),
+ *   never on a schedule), whenever the inner residual has fallen since the
+ *   last update by 1000x (FP32 inner) or 10x (F16 inner), beyond which the
+ *   inner recurrence is not trusted,
  *   and when the inner residual reaches tol.  The solve stops when
  *   ||b - A x|| / ||b|| <= tol in FP64.  The host reads the inner residual
  *   every 10 iterations.

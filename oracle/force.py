@@ -25,7 +25,7 @@ from __future__ import annotations
 
 import numpy as np
 
-from . import dirac
+from . import dirac, solver
 
 
 def outer_spin_sum(a: np.ndarray, b: np.ndarray) -> np.ndarray:
@@ -132,3 +132,29 @@ def link_gradient_at(X, Y, U, c0, links, bc=dirac.DEFAULT_BC) -> np.ndarray:
 def su3_force_at(G, U_links) -> np.ndarray:
     """TA(G U^dag) for gathered links ([n][3][3] each)."""
     return traceless_antihermitian(G @ dirac.dagger3(U_links))
+
+
+def _xy_fields(v_e, U, bc):
+    """(v, D_oe v) and (v, (D_eo)^dag v) as full fields."""
+    ve = dirac.project(v_e, 0)
+    return ve + dirac.moe(ve, U, bc), ve + dirac.moe(ve, U, bc, dagger=True)
+
+
+def normal_solve_vjp(x_e, g_e, U, kappa, bc=dirac.DEFAULT_BC, tol=1e-13):
+    """Vector-Jacobian product of x = A^-1 b, A = Mhat^dag Mhat (even sites).
+
+    For dL = Re(g^dag dx):  dL/db = lambda = A^-1 g (A is hermitian), and
+    dx = -A^-1 dA x gives dL = -Re(lambda^dag dA x) with
+    dA = dMhat^dag Mhat + Mhat^dag dMhat and
+    Re(a^dag dMhat b) = -kappa^2 Re(Y(a)^dag dD_hop X(b)),
+    X(b) = (b, D_oe b), Y(a) = (a, (D_eo)^dag a), so
+    dL = kappa^2 [Re(Y(Mhat x)^dag dD X(lambda)) + Re(Y(Mhat lambda)^dag dD X(x))].
+    Returns (lambda, raw link gradient G).
+    """
+    lam, _, _ = solver.solve_normal(g_e, U, kappa, bc, tol=tol)
+    X1, _ = _xy_fields(lam, U, bc)
+    _, Y1 = _xy_fields(dirac.mhat(x_e, U, kappa, bc), U, bc)
+    X2, _ = _xy_fields(x_e, U, bc)
+    _, Y2 = _xy_fields(dirac.mhat(lam, U, kappa, bc), U, bc)
+    G = link_gradient(X1, Y1, U, kappa ** 2, bc) + link_gradient(X2, Y2, U, kappa ** 2, bc)
+    return lam, G

@@ -10,4 +10,4 @@ from .lqcd import (  # noqa: F401
     dslash, wilson, meo, moe, mhat, dot, norm2, axpby, convert,
     cg_workspace, cg_solve, fermion_force, solve_and_force, cshift, split_rotate, su3_mul,
 )
-from .autograd import WilsonMatrix, wilson_matrix  # noqa: F401
+from .autograd import NormalSolve, WilsonMatrix, normal_solve, wilson_matrix  # noqa: F401

@@ -25,10 +25,14 @@ namespace lqcd {
 constexpr int CG_BLOCK = 256;
 constexpr int CHECK_EVERY = 10;
 // A reduced-precision inner recurrence is trusted only while its residual is
-// within a factor DELTA of the last true residual: past that point the
+// within a factor delta of the last true residual: past that point the
 // computed and true residuals part (rounding of the inner precision), so a
-// reliable update is taken.  FP64 inner iterations need it only at the end.
-constexpr double DELTA = 0.1;
+// reliable update is taken.  delta = 0.1 for binary16 storage (unit roundoff
+// 2^-11), 1e-3 for FP32 (2^-24: after a 1000-fold drop the rounding carried
+// by the recurrence is still ~1e-3 of the residual); FP64 inner iterations
+// need it only at the end.
+constexpr double DELTA_F16 = 0.1;
+constexpr double DELTA_F32 = 1e-3;
 
 enum { S_RR = 0, S_PAP, S_ALPHA, S_RROLD, S_BETA, S_OUT, S_COUNT = 16 };
 enum { OP_ALPHA = 0, OP_RRNEW, OP_RESET, OP_SUM, OP_SETRR };
@@ -310,7 +314,8 @@ struct Solver {
         int k = 0;
         double rr_it = rr;
         double rr_ref = rr;  // true residual at the last reliable update
-        const double drift = P == LQCD_F64 ? 0.0 : DELTA * DELTA;
+        const double delta = P == LQCD_F64 ? 0.0 : P == LQCD_F32 ? DELTA_F32 : DELTA_F16;
+        const double drift = delta * delta;
         while (true) {
             rc = apply_a(P, link, U, w.p, w.ap, w.te, w.to, w.partial);
             if (rc) return rc;

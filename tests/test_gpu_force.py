@@ -232,3 +232,33 @@ def test_solve_and_force_48x3x96():
     want = force.su3_force_at(G, ul)
     got = Fc[idx].cpu().numpy().astype(np.complex128)
     assert rel(got, want) < 2e-6
+
+
+@pytest.mark.parametrize("inner", [(P.F64, 18), (P.F32, 12)])
+def test_normal_solve_vjp_vs_oracle(inner):
+    """Gradients through the solve (adjoint solve + force kernel) against
+    the oracle's vector-Jacobian product."""
+    dims = (8, 4, 4, 8)
+    lat = P.Lattice(dims)
+    U, b = LI.workload_fields(37, dims)
+    b = dirac.project(b, 0)
+    g = dirac.project(LI.gaussian_spinor(np.random.default_rng(38), dims), 0)
+    tb = dev(b).requires_grad_(True)
+    tU = dev(U).requires_grad_(True)
+    x = P.normal_solve(tb, tU, KAPPA, lat, *inner, tol=1e-13)
+    x.backward(dev(g))
+    xo, _, _ = solver.solve_normal(b, U, KAPPA, tol=1e-14)
+    lam, G = force.normal_solve_vjp(xo, g, U, KAPPA, tol=1e-14)
+    assert rel(host(x), xo) < 1e-11
+    assert rel(host(tb.grad), lam) < 1e-11
+    assert rel(host(tU.grad), G) < 1e-10
+
+
+def test_normal_solve_gradcheck_2x4():
+    dims = (2, 2, 2, 2)
+    lat = P.Lattice(dims)
+    U, b = LI.workload_fields(39, dims)
+    tb = dev(dirac.project(b, 0)).requires_grad_(True)
+    tU = dev(U).requires_grad_(True)
+    f = lambda bb, uu: P.normal_solve(bb, uu, KAPPA, lat, P.F64, P.LINK18, tol=1e-13)  # noqa: E731
+    assert torch.autograd.gradcheck(f, (tb, tU), eps=1e-5, atol=1e-6, rtol=1e-5)

@@ -599,3 +599,38 @@ def test_su3_product_pins():
     assert np.abs(LI.det3(W) - 1).max() < 1e-14
     eye = links.su3_product(U, U, adj_u=True)
     assert np.abs(eye - np.eye(3)).max() < 1e-14
+
+
+def test_normal_solve_vjp_finite_differences():
+    """L = Re(g^dag A(U)^-1 b) differentiated by tight solves on 2^3x4."""
+    dims = (2, 2, 2, 4)
+    U, b = LI.workload_fields(25, dims)
+    b = dirac.project(b, 0)
+    g = dirac.project(LI.gaussian_spinor(np.random.default_rng(26), dims), 0)
+
+    def L(uu, bb):
+        x, _, _ = solver.solve_normal(bb, uu, KAPPA, BC, tol=1e-14, maxiter=5000)
+        return np.vdot(g, x).real
+
+    x, _, _ = solver.solve_normal(b, U, KAPPA, BC, tol=1e-14, maxiter=5000)
+    lam, G = force.normal_solve_vjp(x, g, U, KAPPA, BC, tol=1e-14)
+    rng = np.random.default_rng(27)
+    h = 1e-5
+    for _ in range(6):
+        idx = tuple(int(rng.integers(0, n)) for n in U.shape)
+        for part in (1.0, 1j):
+            up = U.copy(); up[idx] += part * h
+            um = U.copy(); um[idx] -= part * h
+            fd = (L(up, b) - L(um, b)) / (2 * h)
+            an = G[idx].real if part == 1.0 else G[idx].imag
+            assert abs(fd - an) <= 1e-6 * max(1.0, abs(an))
+    even = np.argwhere(~LI.parity_mask(dims))
+    for k in range(4):
+        t, z, y, xx = even[int(rng.integers(0, len(even)))]
+        idx = (t, z, y, xx, int(rng.integers(0, 4)), int(rng.integers(0, 3)))
+        for part in (1.0, 1j):
+            bp = b.copy(); bp[idx] += part * h
+            bm = b.copy(); bm[idx] -= part * h
+            fd = (L(U, bp) - L(U, bm)) / (2 * h)
+            an = lam[idx].real if part == 1.0 else lam[idx].imag
+            assert abs(fd - an) <= 1e-6 * max(1.0, abs(an))
