@@ -306,11 +306,13 @@ def run_cg(P, LI, torch, dims, dev):
             U_lo = P.pack_gauge(lat, Ud.to(torch.complex64) if prec == P.F32 else Ud, prec, link)
         ws = P.cg_workspace(lat, prec, link, dev)
         x = P.new_spinor(lat, P.F64, P.EVEN)
-        P.cg_solve(x, b, U_hi, U_lo, KAPPA, tol=1e-10, maxiter=20000,
+        # FP64 true residuals with the same link storage as the inner solve
+        U_rel = U_hi if link == 18 else U_hi12
+        P.cg_solve(x, b, U_rel, U_lo, KAPPA, tol=1e-10, maxiter=20000,
                    reliable_every=rel_every, workspace=ws)  # warm-up (kernel load)
         x.buf.zero_()
         torch.cuda.synchronize()
-        st = P.cg_solve(x, b, U_hi, U_lo, KAPPA, tol=1e-10, maxiter=20000,
+        st = P.cg_solve(x, b, U_rel, U_lo, KAPPA, tol=1e-10, maxiter=20000,
                         reliable_every=rel_every, workspace=ws)
         sols[name] = P.unpack_spinor(x)
         del U_lo

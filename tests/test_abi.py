@@ -120,3 +120,32 @@ def test_product_path_has_no_cpu_fallback():
     psi = torch.zeros(lat.spinor_shape(), dtype=torch.complex128)
     with pytest.raises(RuntimeError):
         P.pack_spinor(lat, psi, P.F64)
+
+
+def test_volume_limit_and_empty_vectors(lib):
+    # a grid of one thread per site must fit 32 bits: V <= 2^31
+    g = geom((1 << 12, 1 << 12, 1 << 8, 2))
+    assert lib.lqcd_spinor_bytes(ctypes.byref(g), 0, 2) == 0
+    ok = geom((1 << 10, 1 << 10, 1 << 10, 2))  # exactly 2^31 sites
+    assert lib.lqcd_spinor_bytes(ctypes.byref(ok), 1, 0) == (1 << 30) * 96
+    # split_rotate: s must divide vl; zero vectors is a no-op
+    a, b = ctypes.c_void_p(4096), ctypes.c_void_p(8192)
+    assert lib.lqcd_split_rotate(a, b, 4, 64, 3, 1, 8, None) == -1
+    assert lib.lqcd_split_rotate(a, b, 4, 64, 4, 1, 12, None) == -1
+    assert lib.lqcd_split_rotate(a, a, 4, 64, 4, 1, 8, None) == -1
+    assert lib.lqcd_split_rotate(a, b, 0, 64, 4, 1, 8, None) == 0
+    # cshift: direction and mu ranges
+    g4 = geom((4, 4, 4, 4))
+    assert lib.lqcd_cshift(ctypes.byref(g4), a, b, 4, 1, 0, None) == -1
+    assert lib.lqcd_cshift(ctypes.byref(g4), a, b, 0, 2, 0, None) == -1
+    # SU(3) product: binary16 is not a product precision
+    assert lib.lqcd_su3_mul(ctypes.byref(g4), a, b, ctypes.c_void_p(12288), 0, 0, 2, 12, None) == -1
+
+
+def test_bench_refuses_several_gpus():
+    import subprocess
+    import sys
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
