@@ -17,8 +17,28 @@
 
 namespace lqcd {
 
+// Cache hints of the hop kernels:
+//  * output stores are non-temporal: the output is not read again by the same
+//    launch, and a later launch reads it on other XCDs, whose L2s do not
+//    share it, so keeping it in this XCD's L2 only evicts the neighbour
+//    spinors held there for reuse;
+//  * link loads are non-temporal when the links plus the input spinor exceed
+//    the 256 MB Infinity Cache in front of HBM; when they fit, plain loads
+//    leave them cached for the next application.
+// Measured (fraction of 8 TB/s, alternating D_eo / D_oe): streaming the
+// output takes FP64-18 from 66.2 to 78.7 at 32^4 and from 64.3 to 68.9 at
+// 48^3x96; cached rather than streamed links take FP32-12 from 71.9 to 80.9
+// at 32^4 (201 MB of links) and FP64-18 from 55.0 to 64.6 at 16^4.  The same
+// hint on the spinor loads would destroy the L2 reuse (LQCD_SPINOR_NT,
+// FP64-18 at 32^4: 50%).  LQCD_OUT_NT / LQCD_LINK_NT = 0 switch a hint off,
+// LQCD_HOP_STREAM = 0..3 forces the mode (ablations).
+#ifndef LQCD_HOP_STREAM
+#define LQCD_HOP_STREAM -1
+#endif
+constexpr int64_t INFINITY_CACHE_BYTES = (int64_t)256 << 20;
+
 // Epilogue shared by both kernel shapes: out = alpha acc + beta y, optional |out|^2.
-template <int P, bool HASY, bool NORM>
+template <int P, bool HASY, bool NORM, bool NT>
 __device__ __forceinline__ double hop_epilogue(const HopArgs &a, int p, int64_t s,
                                                cplx<typename real_of<P>::type> acc[12]) {
     using T = typename real_of<P>::type;
@@ -41,7 +61,7 @@ __device__ __forceinline__ double hop_epilogue(const HopArgs &a, int p, int64_t 
         for (int k = 0; k < 12; ++k) t += norm2(acc[k]);
         nrm = (double)t;
     }
-    store_spinor<P>(a.out[p], s, acc);
+    store_spinor<P, NT>(a.out[p], s, acc);
     return nrm;
 }
 
@@ -55,7 +75,7 @@ __device__ __forceinline__ int64_t hop_site_index(const HopArgs &a, int lane, in
 
 // 4-way shape: wave w computes both hops of direction w; waves 1..3 leave
 // their partial spinors in LDS and wave 0 adds them up.
-template <int P, int LK, bool DAG, bool HASY, bool NORM>
+template <int P, int LK, bool DAG, bool HASY, bool NORM, int NTM>
 __global__ __launch_bounds__(256) void hop4_kernel(HopArgs a) {
     using T = typename real_of<P>::type;
     __shared__ cplx<T> part[3][12][64];
@@ -72,10 +92,10 @@ __global__ __launch_bounds__(256) void hop4_kernel(HopArgs a) {
     if (active) {
         const Coord c = cb_coords(g, p, s);
         switch (w) {
-            case 0: hop_direction<0, P, LK, DAG>(g, a.in[p], a.U, p, s, c, acc); break;
-            case 1: hop_direction<1, P, LK, DAG>(g, a.in[p], a.U, p, s, c, acc); break;
-            case 2: hop_direction<2, P, LK, DAG>(g, a.in[p], a.U, p, s, c, acc); break;
-            default: hop_direction<3, P, LK, DAG>(g, a.in[p], a.U, p, s, c, acc); break;
+            case 0: hop_direction<0, P, LK, DAG, (NTM & 2) != 0>(g, a.in[p], a.U, p, s, c, acc); break;
+            case 1: hop_direction<1, P, LK, DAG, (NTM & 2) != 0>(g, a.in[p], a.U, p, s, c, acc); break;
+            case 2: hop_direction<2, P, LK, DAG, (NTM & 2) != 0>(g, a.in[p], a.U, p, s, c, acc); break;
+            default: hop_direction<3, P, LK, DAG, (NTM & 2) != 0>(g, a.in[p], a.U, p, s, c, acc); break;
         }
     }
     if (w > 0) {
@@ -89,7 +109,7 @@ __global__ __launch_bounds__(256) void hop4_kernel(HopArgs a) {
         for (int j = 0; j < 3; ++j)
 #pragma unroll
             for (int k = 0; k < 12; ++k) acc[k] = acc[k] + part[j][k][lane];
-        nrm[0] = hop_epilogue<P, HASY, NORM>(a, p, s, acc);
+        nrm[0] = hop_epilogue<P, HASY, NORM, (NTM & 1) != 0>(a, p, s, acc);
     }
     if constexpr (NORM) {
         block_sum<1>(nrm);
@@ -113,7 +133,7 @@ __device__ __forceinline__ void add_staged(const cplx<typename real_of<P>::type>
 // 8-way shape: wave w computes hop w (direction w/2, forward for even w) and
 // stages the two colour vectors of its multiplied half-spinor in LDS; wave 0
 // rebuilds the four spin rows from the eight staged half-spinors.
-template <int P, int LK, bool DAG, bool HASY, bool NORM>
+template <int P, int LK, bool DAG, bool HASY, bool NORM, int NTM>
 __global__ __launch_bounds__(512) void hop8_kernel(HopArgs a) {
     using T = typename real_of<P>::type;
     __shared__ cplx<T> chi[8][6][64];
@@ -128,14 +148,14 @@ __global__ __launch_bounds__(512) void hop8_kernel(HopArgs a) {
         const Coord c = cb_coords(g, p, s);
         cplx<T> x0[3], x1[3];
         switch (w) {
-            case 0: hop_single<0, P, LK, DAG>(g, a.in[p], a.U, p, s, c, x0, x1); break;
-            case 1: hop_single<1, P, LK, DAG>(g, a.in[p], a.U, p, s, c, x0, x1); break;
-            case 2: hop_single<2, P, LK, DAG>(g, a.in[p], a.U, p, s, c, x0, x1); break;
-            case 3: hop_single<3, P, LK, DAG>(g, a.in[p], a.U, p, s, c, x0, x1); break;
-            case 4: hop_single<4, P, LK, DAG>(g, a.in[p], a.U, p, s, c, x0, x1); break;
-            case 5: hop_single<5, P, LK, DAG>(g, a.in[p], a.U, p, s, c, x0, x1); break;
-            case 6: hop_single<6, P, LK, DAG>(g, a.in[p], a.U, p, s, c, x0, x1); break;
-            default: hop_single<7, P, LK, DAG>(g, a.in[p], a.U, p, s, c, x0, x1); break;
+            case 0: hop_single<0, P, LK, DAG, (NTM & 2) != 0>(g, a.in[p], a.U, p, s, c, x0, x1); break;
+            case 1: hop_single<1, P, LK, DAG, (NTM & 2) != 0>(g, a.in[p], a.U, p, s, c, x0, x1); break;
+            case 2: hop_single<2, P, LK, DAG, (NTM & 2) != 0>(g, a.in[p], a.U, p, s, c, x0, x1); break;
+            case 3: hop_single<3, P, LK, DAG, (NTM & 2) != 0>(g, a.in[p], a.U, p, s, c, x0, x1); break;
+            case 4: hop_single<4, P, LK, DAG, (NTM & 2) != 0>(g, a.in[p], a.U, p, s, c, x0, x1); break;
+            case 5: hop_single<5, P, LK, DAG, (NTM & 2) != 0>(g, a.in[p], a.U, p, s, c, x0, x1); break;
+            case 6: hop_single<6, P, LK, DAG, (NTM & 2) != 0>(g, a.in[p], a.U, p, s, c, x0, x1); break;
+            default: hop_single<7, P, LK, DAG, (NTM & 2) != 0>(g, a.in[p], a.U, p, s, c, x0, x1); break;
         }
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
@@ -157,7 +177,7 @@ __global__ __launch_bounds__(512) void hop8_kernel(HopArgs a) {
         add_staged<5, P, DAG>(chi, lane, acc);
         add_staged<6, P, DAG>(chi, lane, acc);
         add_staged<7, P, DAG>(chi, lane, acc);
-        nrm[0] = hop_epilogue<P, HASY, NORM>(a, p, s, acc);
+        nrm[0] = hop_epilogue<P, HASY, NORM, (NTM & 1) != 0>(a, p, s, acc);
     }
     if constexpr (NORM) {
         block_sum<1>(nrm);
@@ -170,10 +190,23 @@ constexpr int hop_shape(int prec) {
                                                                      : LQCD_HOP_SHAPE_F16;
 }
 
+template <int P, int LK, bool DAG, bool HASY, bool NORM, int NTM>
+static void launch_nt(const HopArgs &a, dim3 grid, hipStream_t st) {
+    if constexpr (hop_shape(P) == 8) hop8_kernel<P, LK, DAG, HASY, NORM, NTM><<<grid, 512, 0, st>>>(a);
+    else hop4_kernel<P, LK, DAG, HASY, NORM, NTM><<<grid, 256, 0, st>>>(a);
+}
+
+// The cache hints are template arguments: a run-time choice between two
+// otherwise identical load or store sequences gets merged by the compiler,
+// which then drops the hint.
 template <int P, int LK, bool DAG, bool HASY, bool NORM>
 static void launch_shape(const HopArgs &a, dim3 grid, hipStream_t st) {
-    if constexpr (hop_shape(P) == 8) hop8_kernel<P, LK, DAG, HASY, NORM><<<grid, 512, 0, st>>>(a);
-    else hop4_kernel<P, LK, DAG, HASY, NORM><<<grid, 256, 0, st>>>(a);
+    switch (a.stream) {
+        case 0: launch_nt<P, LK, DAG, HASY, NORM, 0>(a, grid, st); break;
+        case 1: launch_nt<P, LK, DAG, HASY, NORM, 1>(a, grid, st); break;
+        case 2: launch_nt<P, LK, DAG, HASY, NORM, 2>(a, grid, st); break;
+        default: launch_nt<P, LK, DAG, HASY, NORM, 3>(a, grid, st); break;
+    }
 }
 
 template <int P, int LK, bool DAG>
@@ -223,6 +256,11 @@ int hop_launch(const HopArgs &a0, int prec, int link, bool dag, int nparity, hip
     a.bpp = (a.g.vh + HOP_SITES - 1) / HOP_SITES;
     a.xcd = a.xcd && LQCD_HOP_XCD;
     a.bz = brick_height(a.g, prec, &a.plane_tiles);
+    const int64_t spinors = (int64_t)(nparity * half_spinor_bytes(a.g, prec));
+    const int64_t links = (int64_t)gauge_bytes(a.g, prec, link);
+    const bool out_nt = OUT_NT;
+    const bool link_nt = LQCD_LINK_NT && spinors + links > INFINITY_CACHE_BYTES;
+    a.stream = LQCD_HOP_STREAM >= 0 ? LQCD_HOP_STREAM : (out_nt ? 1 : 0) | (link_nt ? 2 : 0);
     dim3 grid((unsigned)(a.bpp * nparity));
     const bool hasy = a.y[0] != nullptr || a.y[1] != nullptr;
     const bool norm = a.partial != nullptr;

@@ -111,7 +111,7 @@ __device__ __forceinline__ void force_direction(const ForceArgs &a, int p, int64
 #pragma unroll
         for (int k = 0; k < 9; ++k) out[k] = out[k] + old[k];
     }
-    store_link<P, 18>(a.F, g.ntiles, p, s, MU, out);
+    store_link<P, 18, OUT_NT>(a.F, g.ntiles, p, s, MU, out);
 }
 
 // One 64-site tile per block; wave w computes the link of direction w for

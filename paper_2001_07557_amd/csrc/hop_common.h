@@ -55,15 +55,15 @@ constexpr int64_t BRICK_L2_BUDGET = (int64_t)LQCD_BRICK_BUDGET_KB << 10;
 #define LQCD_BRICK_PRECS 3
 #endif
 
-// Ends one hop: the accumulator is pinned in registers (an empty asm that
+// Ends one hop: the values carried to the next hop are pinned in registers (an empty asm that
 // reads and writes it) and the scheduler may not move instructions across.
 // Without this the compiler sinks all hop arithmetic below the last load, so
 // every loaded spinor and link stays live at once, the register demand
 // exceeds the file and occupancy collapses to one wave per SIMD.
-template <typename T>
-__device__ __forceinline__ void hop_fence(cplx<T> acc[12]) {
+template <typename T, int N>
+__device__ __forceinline__ void hop_fence(cplx<T> acc[N]) {
 #pragma unroll
-    for (int k = 0; k < 12; ++k) asm volatile("" : "+v"(acc[k].re), "+v"(acc[k].im));
+    for (int k = 0; k < N; ++k) asm volatile("" : "+v"(acc[k].re), "+v"(acc[k].im));
     __builtin_amdgcn_sched_barrier(0);
 }
 
@@ -81,6 +81,7 @@ struct HopArgs {
     // cache-blocked traversal: tiles per (z,t) plane, z-planes per brick
     // (0 = plain tile order)
     int plane_tiles, bz;
+    int stream;           // non-temporal hints: bit 0 output stores, bit 1 link loads
 };
 
 // Tile visited by logical block b (within one parity).  With bricks of bz
@@ -208,7 +209,7 @@ __device__ __forceinline__ int64_t hop_neighbour(const Geom &g, int64_t s, const
 }
 
 // chi of the single hop H (0..7: direction H/2, forward for even H) of site s.
-template <int H, int P, int LK, bool DAG>
+template <int H, int P, int LK, bool DAG, bool LNT>
 __device__ __forceinline__ void hop_single(const Geom &g, const char *__restrict__ in,
                                            const char *__restrict__ U, int p, int64_t s,
                                            const Coord &c, cplx<typename real_of<P>::type> x0[3],
@@ -222,8 +223,8 @@ __device__ __forceinline__ void hop_single(const Geom &g, const char *__restrict
     cplx<T> psi[12], u[9];
     T sgn = flip ? T(-1) : T(1);
     load_spinor_hop<P>(in, nb, psi, sgn);
-    if constexpr (FWD) load_link<P, LK>(U, g.ntiles, p, s, MU, u);
-    else load_link<P, LK>(U, g.ntiles, p ^ 1, nb, MU, u);
+    if constexpr (FWD) load_link<P, LK, LNT>(U, g.ntiles, p, s, MU, u);
+    else load_link<P, LK, LNT>(U, g.ntiles, p ^ 1, nb, MU, u);
     hop_chi<MU, S, !FWD>(psi, u, sgn, x0, x1);
 }
 
@@ -233,34 +234,49 @@ struct HopSign {
     static constexpr int value = (H & 1) == 0 ? (DAG ? 1 : -1) : (DAG ? -1 : 1);
 };
 
-// Forward and backward hops in direction MU for the site s of parity p.
-template <int MU, int P, int LK, bool DAG>
+// Forward and backward hops in direction MU for the site s of parity p.  The
+// two hops use the projectors (1 -/+ g_mu) (swapped for the adjoint), so they
+// share rows 0 and 1 of the rebuild and differ by a sign in rows a0 and a1:
+//   rows 0,1 = chi_f + chi_b,   rows a0,a1 = (unit of the forward hop) (chi_f - chi_b).
+// Only the forward hop's two colour vectors (6 complex numbers) stay live
+// while the backward hop loads, instead of a full 12-row accumulator.
+template <int MU, int P, int LK, bool DAG, bool LNT>
 __device__ __forceinline__ void hop_direction(const Geom &g, const char *__restrict__ in,
                                               const char *__restrict__ U, int p, int64_t s,
                                               const Coord &c, cplx<typename real_of<P>::type> acc[12]) {
     using T = typename real_of<P>::type;
-    // forward hop uses (1 - g) (S = -1), backward (1 + g); the adjoint swaps them
+    using PR = Proj<MU>;
     constexpr int SF = DAG ? 1 : -1;
     constexpr int SB = -SF;
+    constexpr int r0 = SF > 0 ? conj_code(PR::c0) : neg_code(conj_code(PR::c0));
+    constexpr int r1 = SF > 0 ? conj_code(PR::c1) : neg_code(conj_code(PR::c1));
     bool flip_f, flip_b;
     const int64_t fwd = hop_neighbour<MU, true>(g, s, c, flip_f);
     const int64_t bwd = hop_neighbour<MU, false>(g, s, c, flip_b);
+    cplx<T> f[6];
     {
         T sgn = flip_f ? T(-1) : T(1);
         cplx<T> psi[12], u[9];
         load_spinor_hop<P>(in, fwd, psi, sgn);
-        load_link<P, LK>(U, g.ntiles, p, s, MU, u);
-        hop_accumulate<MU, SF, false>(psi, u, sgn, acc);
+        load_link<P, LK, LNT>(U, g.ntiles, p, s, MU, u);
+        hop_chi<MU, SF, false>(psi, u, sgn, f, f + 3);
     }
-    hop_fence(acc);
+    hop_fence<T, 6>(f);
     {
         T sgn = flip_b ? T(-1) : T(1);
-        cplx<T> psi[12], u[9];
+        cplx<T> psi[12], u[9], b[6];
         load_spinor_hop<P>(in, bwd, psi, sgn);
-        load_link<P, LK>(U, g.ntiles, p ^ 1, bwd, MU, u);
-        hop_accumulate<MU, SB, true>(psi, u, sgn, acc);
+        load_link<P, LK, LNT>(U, g.ntiles, p ^ 1, bwd, MU, u);
+        hop_chi<MU, SB, true>(psi, u, sgn, b, b + 3);
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            acc[a] = f[a] + b[a];
+            acc[3 + a] = f[3 + a] + b[3 + a];
+            acc[PR::a0 * 3 + a] = mul_unit<r0>(f[a] - b[a]);
+            acc[PR::a1 * 3 + a] = mul_unit<r1>(f[3 + a] - b[3 + a]);
+        }
     }
-    hop_fence(acc);
+    hop_fence<T, 12>(acc);
 }
 
 }  // namespace lqcd

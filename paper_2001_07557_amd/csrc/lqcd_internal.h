@@ -121,14 +121,24 @@ typedef uint32_t v2u __attribute__((ext_vector_type(2)));
 #define LQCD_LAYOUT_AOS 0
 #endif
 
-// Links are streamed once per application: load them with the non-temporal
-// hint (ablation switch).
+// The stencil kernels (hop, force) store their results with the non-temporal
+// hint: nothing in the launch reads them again, and plain stores would evict
+// the neighbour spinors that the L2 holds for reuse (ablation switch, 0 =
+// plain stores).  Pure streaming kernels have no such reuse to protect and
+// use plain stores.
+#ifndef LQCD_OUT_NT
+#define LQCD_OUT_NT 1
+#endif
+constexpr bool OUT_NT = LQCD_OUT_NT != 0;
+
+// Links are read once per application: by default they are loaded with the
+// non-temporal hint (the hop kernels choose per launch; 0 switches it off).
 #ifndef LQCD_LINK_NT
 #define LQCD_LINK_NT 1
 #endif
-template <typename V>
+template <bool NT, typename V>
 __device__ __forceinline__ V stream_load(const V *p) {
-    if constexpr (LQCD_LINK_NT) return __builtin_nontemporal_load(p);
+    if constexpr (NT) return __builtin_nontemporal_load(p);
     else return *p;
 }
 
@@ -139,7 +149,12 @@ template <> struct real_of<LQCD_F64> { using type = double; };
 // per-site loads and stores, spinors (12 complexes, index spin*3 + colour)
 // ---------------------------------------------------------------------------
 
-template <int P>
+// non-temporal spinor loads (ablation switch; off: the hop kernels rely on the
+// L2 keeping neighbour spinors between the eight hops that read each one)
+#ifndef LQCD_SPINOR_NT
+#define LQCD_SPINOR_NT 0
+#endif
+template <int P, bool NT = (LQCD_SPINOR_NT != 0)>
 __device__ __forceinline__ void load_spinor(const char *__restrict__ base, int64_t s,
                                             cplx<typename real_of<P>::type> v[12]) {
     const int64_t tile = s >> TILE_SHIFT;
@@ -157,23 +172,23 @@ __device__ __forceinline__ void load_spinor(const char *__restrict__ base, int64
         const v2d *w = reinterpret_cast<const v2d *>(t) + lane;
 #pragma unroll
         for (int k = 0; k < 12; ++k) {
-            v2d d = w[k * TILE];
+            v2d d = stream_load<NT>(&w[k * TILE]);
             v[k] = {d.x, d.y};
         }
     } else if constexpr (P == LQCD_F32) {
         const v4f *w = reinterpret_cast<const v4f *>(t) + lane;
 #pragma unroll
         for (int k = 0; k < 6; ++k) {
-            v4f f = w[k * TILE];
+            v4f f = stream_load<NT>(&w[k * TILE]);
             v[2 * k] = {f.x, f.y};
             v[2 * k + 1] = {f.z, f.w};
         }
     } else {
         const v4u *w = reinterpret_cast<const v4u *>(t) + lane;
-        const float sc = reinterpret_cast<const float *>(t + 3 * TILE * WORD)[lane];
+        const float sc = stream_load<NT>(reinterpret_cast<const float *>(t + 3 * TILE * WORD) + lane);
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
-            v4u q = w[k * TILE];
+            v4u q = stream_load<NT>(&w[k * TILE]);
             uint32_t u[4] = {q.x, q.y, q.z, q.w};
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
@@ -214,7 +229,15 @@ __device__ __forceinline__ void load_spinor_hop(const char *__restrict__ base, i
     }
 }
 
-template <int P>
+// Store of one word; NT marks it non-temporal (a result that no later work of
+// the same kernel reads).
+template <bool NT, typename V>
+__device__ __forceinline__ void put(V *p, V v) {
+    if constexpr (NT) __builtin_nontemporal_store(v, p);
+    else *p = v;
+}
+
+template <int P, bool NT = false>
 __device__ __forceinline__ void store_spinor(char *__restrict__ base, int64_t s,
                                              const cplx<typename real_of<P>::type> v[12]) {
     const int64_t tile = s >> TILE_SHIFT;
@@ -231,12 +254,12 @@ __device__ __forceinline__ void store_spinor(char *__restrict__ base, int64_t s,
     } else if constexpr (P == LQCD_F64) {
         v2d *w = reinterpret_cast<v2d *>(t) + lane;
 #pragma unroll
-        for (int k = 0; k < 12; ++k) w[k * TILE] = v2d{v[k].re, v[k].im};
+        for (int k = 0; k < 12; ++k) put<NT>(&w[k * TILE], v2d{v[k].re, v[k].im});
     } else if constexpr (P == LQCD_F32) {
         v4f *w = reinterpret_cast<v4f *>(t) + lane;
 #pragma unroll
         for (int k = 0; k < 6; ++k)
-            w[k * TILE] = v4f{v[2 * k].re, v[2 * k].im, v[2 * k + 1].re, v[2 * k + 1].im};
+            put<NT>(&w[k * TILE], v4f{v[2 * k].re, v[2 * k].im, v[2 * k + 1].re, v[2 * k + 1].im});
     } else {
         float m = 0.f;
 #pragma unroll
@@ -252,9 +275,9 @@ __device__ __forceinline__ void store_spinor(char *__restrict__ base, int64_t s,
                 __half2 h = __floats2half2_rn(v[4 * k + j].re * inv, v[4 * k + j].im * inv);
                 u[j] = *reinterpret_cast<uint32_t *>(&h);
             }
-            w[k * TILE] = v4u{u[0], u[1], u[2], u[3]};
+            put<NT>(&w[k * TILE], v4u{u[0], u[1], u[2], u[3]});
         }
-        reinterpret_cast<float *>(t + 3 * TILE * WORD)[lane] = m;
+        put<NT>(reinterpret_cast<float *>(t + 3 * TILE * WORD) + lane, m);
     }
 }
 
@@ -277,7 +300,7 @@ __device__ __forceinline__ const char *link_tile(const char *U, int64_t ntiles, 
     return U + (((int64_t)p * ntiles + tile) * 4 + mu) * (int64_t)link_tile_bytes(P, LK);
 }
 
-template <int P, int LK>
+template <int P, int LK, bool NT = (LQCD_LINK_NT != 0)>
 __device__ __forceinline__ void load_link(const char *__restrict__ U, int64_t ntiles, int p,
                                           int64_t s, int mu,
                                           cplx<typename real_of<P>::type> u[9]) {
@@ -291,10 +314,10 @@ __device__ __forceinline__ void load_link(const char *__restrict__ U, int64_t nt
 #pragma unroll
         for (int k = 0; k < n; ++k) {
             if constexpr (P == LQCD_F64) {
-                v2d d = stream_load(reinterpret_cast<const v2d *>(l) + k);
+                v2d d = stream_load<NT>(reinterpret_cast<const v2d *>(l) + k);
                 u[k] = {d.x, d.y};
             } else {
-                v2f d = stream_load(reinterpret_cast<const v2f *>(l) + k);
+                v2f d = stream_load<NT>(reinterpret_cast<const v2f *>(l) + k);
                 u[k] = {d.x, d.y};
             }
         }
@@ -303,7 +326,7 @@ __device__ __forceinline__ void load_link(const char *__restrict__ U, int64_t nt
         constexpr int n = LK == 18 ? 9 : 6;
 #pragma unroll
         for (int k = 0; k < n; ++k) {
-            v2d d = stream_load(&w[k * TILE]);
+            v2d d = stream_load<NT>(&w[k * TILE]);
             u[k] = {d.x, d.y};
         }
     } else if constexpr (P == LQCD_F32) {
@@ -311,20 +334,20 @@ __device__ __forceinline__ void load_link(const char *__restrict__ U, int64_t nt
         constexpr int n4 = LK == 18 ? 4 : 3;
 #pragma unroll
         for (int k = 0; k < n4; ++k) {
-            v4f f = stream_load(&w[k * TILE]);
+            v4f f = stream_load<NT>(&w[k * TILE]);
             u[2 * k] = {f.x, f.y};
             u[2 * k + 1] = {f.z, f.w};
         }
         if constexpr (LK == 18) {
             const v2f *w2 = reinterpret_cast<const v2f *>(t + 4 * TILE * WORD) + lane;
-            v2f f = stream_load(w2);
+            v2f f = stream_load<NT>(w2);
             u[8] = {f.x, f.y};
         }
     } else {
         const v4u *w = reinterpret_cast<const v4u *>(t) + lane;
-        v4u q = stream_load(w);
+        v4u q = stream_load<NT>(w);
         const v2u *w2 = reinterpret_cast<const v2u *>(t + TILE * WORD) + lane;
-        v2u q2 = stream_load(w2);
+        v2u q2 = stream_load<NT>(w2);
         uint32_t a[6] = {q.x, q.y, q.z, q.w, q2.x, q2.y};
 #pragma unroll
         for (int j = 0; j < 6; ++j) {
@@ -337,7 +360,7 @@ __device__ __forceinline__ void load_link(const char *__restrict__ U, int64_t nt
 }
 
 // Store a link in the layout (rows 0, 1 only for LINK12).
-template <int P, int LK>
+template <int P, int LK, bool NT = false>
 __device__ __forceinline__ void store_link(char *__restrict__ U, int64_t ntiles, int p,
                                            int64_t s, int mu,
                                            const cplx<typename real_of<P>::type> u[9]) {
@@ -356,16 +379,16 @@ __device__ __forceinline__ void store_link(char *__restrict__ U, int64_t ntiles,
         v2d *w = reinterpret_cast<v2d *>(t) + lane;
         constexpr int n = LK == 18 ? 9 : 6;
 #pragma unroll
-        for (int k = 0; k < n; ++k) w[k * TILE] = v2d{u[k].re, u[k].im};
+        for (int k = 0; k < n; ++k) put<NT>(&w[k * TILE], v2d{u[k].re, u[k].im});
     } else if constexpr (P == LQCD_F32) {
         v4f *w = reinterpret_cast<v4f *>(t) + lane;
         constexpr int n4 = LK == 18 ? 4 : 3;
 #pragma unroll
         for (int k = 0; k < n4; ++k)
-            w[k * TILE] = v4f{u[2 * k].re, u[2 * k].im, u[2 * k + 1].re, u[2 * k + 1].im};
+            put<NT>(&w[k * TILE], v4f{u[2 * k].re, u[2 * k].im, u[2 * k + 1].re, u[2 * k + 1].im});
         if constexpr (LK == 18) {
             v2f *w2 = reinterpret_cast<v2f *>(t + 4 * TILE * WORD) + lane;
-            *w2 = v2f{u[8].re, u[8].im};
+            put<NT>(w2, v2f{u[8].re, u[8].im});
         }
     } else {
         uint32_t a[6];
@@ -375,9 +398,9 @@ __device__ __forceinline__ void store_link(char *__restrict__ U, int64_t ntiles,
             a[j] = *reinterpret_cast<uint32_t *>(&h);
         }
         v4u *w = reinterpret_cast<v4u *>(t) + lane;
-        *w = v4u{a[0], a[1], a[2], a[3]};
+        put<NT>(w, v4u{a[0], a[1], a[2], a[3]});
         v2u *w2 = reinterpret_cast<v2u *>(t + TILE * WORD) + lane;
-        *w2 = v2u{a[4], a[5]};
+        put<NT>(w2, v2u{a[4], a[5]});
     }
 }
 
