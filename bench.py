@@ -53,13 +53,17 @@ def log(msg: str) -> None:
 
 
 def source_hash() -> str:
-    """Hash of the hop kernels' sources: a counter summary taken for another
-    version of the kernel no longer applies."""
+    """Hash of the hop kernels' code (comments and whitespace removed): a
+    counter summary taken for another version of the kernel no longer
+    applies, while an edited comment leaves the kernel, and the hash, as it
+    was."""
     h = hashlib.sha256()
     d = os.path.join(ROOT, "paper_2001_07557_amd", "csrc")
     for f in HOP_SOURCES:
-        with open(os.path.join(d, f), "rb") as fh:
-            h.update(f.encode() + fh.read())
+        with open(os.path.join(d, f)) as fh:
+            code = re.sub(r"/\*.*?\*/", " ", fh.read(), flags=re.S)
+        code = re.sub(r"//[^\n]*", " ", code)
+        h.update(f.encode() + " ".join(code.split()).encode())
     return h.hexdigest()[:16]
 
 
