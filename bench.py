@@ -9,7 +9,12 @@ variant is FP32 arithmetic with 12-real links; every storage variant (FP64 and
 FP32 with 18- and 12-real links, binary16 storage) is timed the same way and
 reported under "variants".  The solve of the 32^4 smoothed-link system
 (FP64 CG vs mixed FP32 / binary16 inner solvers to a 1e-10 true residual) is
-reported under "cg".
+reported under "cg", the 48^3x96 solve plus force under "solve_force", the
+paper's building blocks under "building_blocks".  "sweep" repeats the hop
+timing on 24^4, 32^4 and 48^3x96, and on the benchmark lattice with a
+rotating pool of input copies larger than the Infinity Cache, each also as a
+fraction of a measured copy bandwidth; "grad" times the differentiated
+operator (forward M psi, backward M^dag g and link force) on 24^4.
 
 Timing: one step is captured into a HIP graph (torch.cuda.CUDAGraph around
 the library calls) and replayed; HIP events on the stream the graph is
@@ -128,6 +133,12 @@ def main():
     ap.add_argument("--library", default=None,
                     help="load this liblqcd.so instead of the in-tree one (ablation builds "
                          "from python -m paper_2001_07557_amd.build -D ... --out DIR)")
+    ap.add_argument("--no-sweep", action="store_true",
+                    help="skip the lattice sweep (16^4 from a rotating input pool, 24^4, 32^4, "
+                         "48^3x96) and the copy-bandwidth measurement")
+    ap.add_argument("--no-grad", action="store_true",
+                    help="skip the forward / backward timing of the differentiated operator")
+    ap.add_argument("--grad-lattice", default="24,24,24,24")
     ap.add_argument("--reductions", action="store_true",
                     help="only time <a,b> and |a|^2 on the lattice and count distinct results")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
@@ -183,10 +194,8 @@ def main():
         torch.cuda.empty_cache()
         log("building blocks done")
     lattice = tuple(int(v) for v in args.lattice.split(","))
-    lat = P.Lattice(lattice)
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
-    U, psi = LI.workload_fields_device(1, lattice, dev)
 
     variants = VARIANTS
     if args.only:
@@ -194,60 +203,27 @@ def main():
         variants = [(p, int(l))]
     results = {}
     headline = None
+    U, psi = LI.workload_fields_device(1, lattice, dev)
     for var in variants:
-        prec = prec_of[var[0]]
-        tdt = torch.complex64 if prec == P.F32 else torch.complex128
-        Uf = P.pack_gauge(lat, U.to(tdt), prec, var[1])
-        odd_in = P.pack_spinor(lat, psi.to(tdt), prec, P.ODD)
-        even_in = P.pack_spinor(lat, psi.to(tdt), prec, P.EVEN)
-        even_out = P.new_spinor(lat, prec, P.EVEN)
-        odd_out = P.new_spinor(lat, prec, P.ODD)
-
-        def step():
-            # same inputs every application, outputs overwritten
-            for _ in range(args.apps):
-                P.meo(even_out, odd_in, Uf)
-                P.moe(odd_out, even_in, Uf)
-
-        # one step is captured once into a HIP graph and replayed: at 16^4 a
-        # launch from the host costs about as much as the kernel itself
-        step()
-        torch.cuda.synchronize()
-        graph = None
-        if not args.eager:
-            graph = torch.cuda.CUDAGraph()
-            with torch.cuda.graph(graph):
-                step()
-            torch.cuda.synchronize()
-        run = graph.replay if graph is not None else step
-        for _ in range(args.warmup):
-            run()
-        stream = torch.cuda.current_stream()
-        torch.cuda.synchronize()
-        e0 = torch.cuda.Event(enable_timing=True)
-        e1 = torch.cuda.Event(enable_timing=True)
-        e0.record(stream)
-        for _ in range(args.steps):
-            run()
-        e1.record(stream)
-        torch.cuda.synchronize()
-        ms = e0.elapsed_time(e1)
-        del graph
-        launches = 2 * args.apps * args.steps
-        t_launch = ms * 1e-3 / launches
-        vh = lat.half_volume
-        bytes_launch = BYTES_SITE[var] * vh
-        gflops = FLOP_SITE * vh / t_launch / 1e9
-        gbs = bytes_launch / t_launch / 1e9
-        results[f"{var[0]}-{var[1]}"] = {
-            "gflops": round(gflops, 1), "gbs": round(gbs, 1), "frac_hbm": round(gbs / PEAK_HBM, 4),
-            "us_per_launch": round(t_launch * 1e6, 3), "bytes_per_site": BYTES_SITE[var]}
+        r = time_hop(P, torch, lattice, U, psi, var, args.apps, args.steps, args.warmup,
+                     eager=args.eager)
+        results[f"{var[0]}-{var[1]}"] = r["entry"]
         if var == HEADLINE or args.only:
-            headline = (var, ms, t_launch, bytes_launch, gflops, gbs)
-        log(f"{var[0]}-{var[1]}: {gflops:.1f} GFlop/s, {gbs:.1f} GB/s")
-        del Uf, odd_in, even_in, even_out, odd_out
+            headline = (var, r["ms"], r["t_launch"], r["bytes_launch"], r["gflops"], r["gbs"])
+        log(f"{var[0]}-{var[1]}: {r['gflops']:.1f} GFlop/s, {r['gbs']:.1f} GB/s")
     del U, psi
     torch.cuda.empty_cache()
+
+    sweep = None
+    if not args.no_sweep and not args.only:
+        sweep = run_sweep(P, LI, torch, lattice, dev)
+        torch.cuda.empty_cache()
+        log("lattice sweep done")
+    grad = None
+    if not args.no_grad:
+        grad = run_grad(P, LI, torch, tuple(int(v) for v in args.grad_lattice.split(",")), dev)
+        torch.cuda.empty_cache()
+        log("gradient section done")
 
     var, ms, t_launch, bytes_launch, gflops, gbs = headline
     traffic = measured_traffic(lattice, var)
@@ -279,6 +255,10 @@ def main():
         },
         "variants": results,
     }
+    if sweep is not None:
+        line["sweep"] = sweep
+    if grad is not None:
+        line["grad"] = grad
     if cg is not None:
         line["cg"] = cg
     if solve_force is not None:
@@ -289,6 +269,170 @@ def main():
         log("timing the CPU oracle")
         line["cpu_baseline"] = cpu_baseline(lattice)
     print(json.dumps(line), flush=True)
+
+
+def time_hop(P, torch, lattice, U, psi, var, apps, steps, warmup, eager=False, pool=1):
+    """Alternating D_eo / D_oe launches (`apps` of each per step) of one storage
+    variant, timed with HIP events over `steps` graph replays.  With pool > 1
+    application i reads the i-th of `pool` copies of the links and inputs, so
+    a launch finds none of its data in the caches from the previous one."""
+    prec = {"f64": P.F64, "f32": P.F32, "f16": P.F16}[var[0]]
+    lat = P.Lattice(lattice)
+    tdt = torch.complex64 if prec == P.F32 else torch.complex128
+    Uf = [P.pack_gauge(lat, U.to(tdt), prec, var[1])]
+    odd_in = [P.pack_spinor(lat, psi.to(tdt), prec, P.ODD)]
+    even_in = [P.pack_spinor(lat, psi.to(tdt), prec, P.EVEN)]
+    for _ in range(pool - 1):
+        Uf.append(P.GaugeField(lat, prec, var[1], Uf[0].buf.clone()))
+        odd_in.append(P.SpinorField(lat, prec, P.ODD, odd_in[0].buf.clone()))
+        even_in.append(P.SpinorField(lat, prec, P.EVEN, even_in[0].buf.clone()))
+    even_out = P.new_spinor(lat, prec, P.EVEN)
+    odd_out = P.new_spinor(lat, prec, P.ODD)
+
+    def step():
+        # fixed inputs, outputs overwritten
+        for i in range(apps):
+            k = i % pool
+            P.meo(even_out, odd_in[k], Uf[k])
+            P.moe(odd_out, even_in[k], Uf[k])
+
+    # one step is captured once into a HIP graph and replayed: at 16^4 a
+    # launch from the host costs about as much as the kernel itself
+    step()
+    torch.cuda.synchronize()
+    graph = None
+    if not eager:
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph):
+            step()
+        torch.cuda.synchronize()
+    run = graph.replay if graph is not None else step
+    for _ in range(warmup):
+        run()
+    stream = torch.cuda.current_stream()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(steps):
+        run()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    del graph
+    t_launch = ms * 1e-3 / (2 * apps * steps)
+    vh = lat.half_volume
+    bytes_launch = BYTES_SITE[var] * vh
+    gflops = FLOP_SITE * vh / t_launch / 1e9
+    gbs = bytes_launch / t_launch / 1e9
+    entry = {"gflops": round(gflops, 1), "gbs": round(gbs, 1), "frac_hbm": round(gbs / PEAK_HBM, 4),
+             "us_per_launch": round(t_launch * 1e6, 3), "bytes_per_site": BYTES_SITE[var]}
+    return {"entry": entry, "ms": ms, "t_launch": t_launch, "bytes_launch": bytes_launch,
+            "gflops": gflops, "gbs": gbs}
+
+
+def copy_bandwidth(P, torch, dims=(48, 48, 48, 96), reps=10):
+    """Read + write bandwidth of a plain streaming copy through the library
+    (lqcd_convert between two FP64 full spinor fields, 2 GB each)."""
+    lat = P.Lattice(dims)
+    src = P.new_spinor(lat, P.F64, P.FULL)
+    src.buf.fill_(1)
+    dst = P.new_spinor(lat, P.F64, P.FULL)
+    t = _time_graph(torch, lambda: P.convert(dst, src), reps=reps)
+    gbs = 2 * 192 * lat.volume / t / 1e9
+    del src, dst
+    return {"gbs": round(gbs, 1), "frac_hbm": round(gbs / PEAK_HBM, 4),
+            "what": f"lqcd_convert FP64 -> FP64 full spinor field, {'x'.join(map(str, dims))}, "
+                    "bytes read + written"}
+
+
+def run_sweep(P, LI, torch, lattice, dev, apps=20, steps=5, warmup=2):
+    """Every storage variant on the lattices the bandwidth claim is made on,
+    the benchmark lattice again with a rotating pool of input copies larger
+    than the 256 MB Infinity Cache (so its launches read HBM), and each
+    fraction also against the measured copy bandwidth."""
+    copy = copy_bandwidth(P, torch)
+    torch.cuda.empty_cache()
+    out = {"copy": copy, "apps_per_step": apps, "steps": steps}
+    cases = [(lattice, "pool")] + [(d, "plain") for d in ((24, 24, 24, 24), (32, 32, 32, 32),
+                                                           (48, 48, 48, 96))]
+    for dims, kind in cases:
+        U, psi = LI.workload_fields_device(1, dims, dev)
+        lat = P.Lattice(dims)
+        key = "x".join(map(str, dims)) + ("_pool" if kind == "pool" else "")
+        row = {}
+        for var in VARIANTS:
+            pool = 1
+            if kind == "pool":
+                prec = {"f64": P.F64, "f32": P.F32, "f16": P.F16}[var[0]]
+                per_copy = lat.gauge_bytes(prec, var[1]) + 2 * lat.spinor_bytes(prec, P.EVEN)
+                pool = max(2, -(-(512 << 20) // per_copy))
+            # every copy is read once per step: more than 512 MB between two
+            # reads of the same data
+            r = time_hop(P, torch, dims, U, psi, var, max(apps, pool), steps, warmup, pool=pool)
+            e = r["entry"]
+            e["frac_copy"] = round(r["gbs"] / copy["gbs"], 4)
+            if pool > 1:
+                e["pool"] = pool
+            row[f"{var[0]}-{var[1]}"] = e
+            torch.cuda.empty_cache()
+        out[key] = row
+        log(f"sweep {key}: " + ", ".join(f"{k} {v['frac_hbm'] * 100:.1f}%" for k, v in row.items()))
+        del U, psi
+        torch.cuda.empty_cache()
+    return out
+
+
+def run_grad(P, LI, torch, dims, dev, kappa=KAPPA):
+    """The differentiated operator on one lattice: forward M psi and the two
+    backward kernels (M^dag g and the link force) as HIP-graph replays, with
+    bytes per site read and written, and the end-to-end autograd step
+    (packing included) for context."""
+    from paper_2001_07557_amd.autograd import wilson_matrix
+    lat = P.Lattice(dims)
+    U, psi = LI.workload_fields_device(4, dims, dev)
+    g = torch.randn(psi.shape, dtype=torch.complex128, device=dev,
+                    generator=torch.Generator(device=dev).manual_seed(4004))
+    out = {"lattice": list(dims), "kappa": kappa}
+    v = lat.volume
+    for name, prec, tdt, rb, sb in (("f64-18", P.F64, torch.complex128, 144, 192),
+                                   ("f32-18", P.F32, torch.complex64, 72, 96)):
+        Uf = P.pack_gauge(lat, U.to(tdt), prec, 18)
+        pf = P.pack_spinor(lat, psi.to(tdt), prec)
+        gf = P.pack_spinor(lat, g.to(tdt), prec)
+        of = P.new_spinor(lat, prec, P.FULL)
+        F = P.new_gauge(lat, prec, 18)
+        t_fwd = _time_graph(torch, lambda: P.wilson(of, pf, Uf, kappa))
+        t_dag = _time_graph(torch, lambda: P.wilson(of, gf, Uf, kappa, dagger=True))
+        t_force = _time_graph(torch, lambda: P.fermion_force(pf, gf, Uf, -kappa, mode=0, out=F))
+        # M: 4 links (each read by its two end sites), psi once as neighbour
+        # and once for the diagonal, the output; force: 4 links, X, Y, 4 force links
+        b_m = v * (4 * rb + 3 * sb)
+        b_f = v * (4 * rb + 2 * sb + 4 * rb)
+        psi_t = psi.to(tdt).clone().requires_grad_(True)
+        U_t = U.to(tdt).clone().requires_grad_(True)
+        g_t = g.to(tdt)
+
+        def autograd_step():
+            y = wilson_matrix(psi_t, U_t, kappa, lat, prec=prec, link=18)
+            y.backward(g_t)
+
+        autograd_step()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(5):
+            autograd_step()
+        torch.cuda.synchronize()
+        t_ag = (time.perf_counter() - t0) / 5
+        out[name] = {
+            "forward_us": round(t_fwd * 1e6, 1), "forward_gbs": round(b_m / t_fwd / 1e9, 1),
+            "dagger_us": round(t_dag * 1e6, 1), "dagger_gbs": round(b_m / t_dag / 1e9, 1),
+            "force_us": round(t_force * 1e6, 1), "force_gbs": round(b_f / t_force / 1e9, 1),
+            "autograd_step_ms": round(t_ag * 1e3, 3),
+        }
+        del Uf, pf, gf, of, F, psi_t, U_t, g_t
+        torch.cuda.empty_cache()
+    return out
 
 
 def run_cg(P, LI, torch, dims, dev):
@@ -322,7 +466,10 @@ def run_cg(P, LI, torch, dims, dev):
         del U_lo
         out[name] = {"seconds": round(st.seconds, 4), "iterations": st.iterations,
                      "reliable_updates": st.reliable_updates,
-                     "true_residual": st.true_residual}
+                     "true_residual": st.true_residual,
+                     # hop flops of the inner iterations over the whole solve time
+                     "effective_hop_gflops": round(
+                         4 * FLOP_SITE * lat.half_volume * st.iterations / st.seconds / 1e9, 1)}
     ref = sols["f64"]
     for name in ("f64-12", "f32-12", "f16-12"):
         out[name]["rel_err_vs_f64_solution"] = float(

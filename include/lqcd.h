@@ -199,7 +199,9 @@ int lqcd_norm2(const lqcd_geom_t *g, int subset, const void *a, int prec,
 int lqcd_axpby(const lqcd_geom_t *g, int subset, double a, const void *x, double b,
                void *y, int prec, void *stream);
 
-/* dst = src with a change of storage precision (same subset). */
+/* dst = src with a change of storage precision (same subset).  With equal
+ * precisions it is a byte copy of the internal layout (bit-exact, also for
+ * binary16 storage). */
 int lqcd_convert(const lqcd_geom_t *g, int subset, void *dst, int dst_prec,
                  const void *src, int src_prec, void *stream);
 

@@ -117,22 +117,33 @@ __global__ __launch_bounds__(RED_BLOCK) void convert_k(char *dst, const char *sr
     store_spinor<PD>(dst + (hi ? hbd : 0), s, w);
 }
 
+// Same storage precision: the layouts agree byte for byte, so the copy is one
+// 16-byte word per thread (a thread per site moving all its words measured
+// 5.3 TB/s on a 4 GB copy against 6.2 TB/s for one word per thread).
+__global__ __launch_bounds__(RED_BLOCK) void copy_words_k(v4u *dst, const v4u *src, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) dst[i] = src[i];
+}
+
 void launch_convert(const Geom &g, int nhalf, char *dst, int pd, const char *src, int ps,
                     hipStream_t st) {
+    if (pd == ps) {
+        const int64_t words = (int64_t)half_spinor_bytes(g, pd) * nhalf / 16;
+        dim3 grid((unsigned)((words + RED_BLOCK - 1) / RED_BLOCK)), block(RED_BLOCK);
+        copy_words_k<<<grid, block, 0, st>>>((v4u *)dst, (const v4u *)src, words);
+        return;
+    }
     const int64_t n = g.vh * nhalf;
     dim3 grid((unsigned)((n + RED_BLOCK - 1) / RED_BLOCK)), block(RED_BLOCK);
     const int64_t hbd = (int64_t)half_spinor_bytes(g, pd), hbs = (int64_t)half_spinor_bytes(g, ps);
 #define LQCD_CONV(A, B) \
     if (pd == A && ps == B) { convert_k<A, B><<<grid, block, 0, st>>>(dst, src, g.vh, nhalf, hbd, hbs); return; }
-    LQCD_CONV(LQCD_F64, LQCD_F64)
     LQCD_CONV(LQCD_F64, LQCD_F32)
     LQCD_CONV(LQCD_F64, LQCD_F16)
     LQCD_CONV(LQCD_F32, LQCD_F64)
-    LQCD_CONV(LQCD_F32, LQCD_F32)
     LQCD_CONV(LQCD_F32, LQCD_F16)
     LQCD_CONV(LQCD_F16, LQCD_F64)
     LQCD_CONV(LQCD_F16, LQCD_F32)
-    LQCD_CONV(LQCD_F16, LQCD_F16)
 #undef LQCD_CONV
 }
 

@@ -65,6 +65,15 @@ def test_axpby_and_convert():
     h = P.new_spinor(lat, P.F16, P.ODD)
     P.convert(h, x)
     assert np.array_equal(host(P.unpack_spinor(h)), dirac.project(links.round_f16_spinor(a), 1))
+    # equal precisions: a byte copy of the internal layout, full fields too
+    for src in (x, z, h):
+        dst = P.new_spinor(lat, src.prec, P.ODD)
+        P.convert(dst, src)
+        assert torch.equal(dst.buf, src.buf)
+    full = P.pack_spinor(lat, dev(a), P.F16, P.FULL)
+    dst = P.new_spinor(lat, P.F16, P.FULL)
+    P.convert(dst, full)
+    assert torch.equal(dst.buf, full.buf)
 
 
 # ----------------------------------------------------------------------------
