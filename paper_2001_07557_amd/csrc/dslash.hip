@@ -112,8 +112,12 @@ __global__ __launch_bounds__(256) void hop4_kernel(HopArgs a) {
         nrm[0] = hop_epilogue<P, HASY, NORM, (NTM & 1) != 0>(a, p, s, acc);
     }
     if constexpr (NORM) {
-        block_sum<1>(nrm);
-        if (threadIdx.x == 0) a.partial[blk] = nrm[0];
+        // wave 0 holds every site of the tile: a wave reduction suffices and
+        // the other waves leave after the staging barrier
+        if (w == 0) {
+            const double t = wave_sum(nrm[0]);
+            if (lane == 0) a.partial[blk] = t;
+        }
     }
 }
 
@@ -180,8 +184,12 @@ __global__ __launch_bounds__(512) void hop8_kernel(HopArgs a) {
         nrm[0] = hop_epilogue<P, HASY, NORM, (NTM & 1) != 0>(a, p, s, acc);
     }
     if constexpr (NORM) {
-        block_sum<1>(nrm);
-        if (threadIdx.x == 0) a.partial[blk] = nrm[0];
+        // wave 0 holds every site of the tile: a wave reduction suffices and
+        // the other waves leave after the staging barrier
+        if (w == 0) {
+            const double t = wave_sum(nrm[0]);
+            if (lane == 0) a.partial[blk] = t;
+        }
     }
 }
 
