@@ -24,7 +24,9 @@ namespace lqcd {
 //    spinors held there for reuse;
 //  * link loads are non-temporal when the links plus the input spinor exceed
 //    the 256 MB Infinity Cache in front of HBM; when they fit, plain loads
-//    leave them cached for the next application.
+//    leave them cached for the next application.  A launch over both
+//    parities uses every link twice and always loads them plainly (48^3x96
+//    full-lattice M, FP32-18: 4.3 -> 5.0 TB/s).
 // Measured (fraction of 8 TB/s, alternating D_eo / D_oe): streaming the
 // output takes FP64-18 from 66.2 to 78.7 at 32^4 and from 64.3 to 68.9 at
 // 48^3x96; cached rather than streamed links take FP32-12 from 71.9 to 80.9
@@ -34,6 +36,10 @@ namespace lqcd {
 // LQCD_HOP_STREAM = 0..3 forces the mode (ablations).
 #ifndef LQCD_HOP_STREAM
 #define LQCD_HOP_STREAM -1
+#endif
+// both-parity launches pair the even and odd tile of a region (ablation switch)
+#ifndef LQCD_HOP_PAIRED
+#define LQCD_HOP_PAIRED 1
 #endif
 constexpr int64_t INFINITY_CACHE_BYTES = (int64_t)256 << 20;
 
@@ -65,9 +71,16 @@ __device__ __forceinline__ double hop_epilogue(const HopArgs &a, int p, int64_t 
     return nrm;
 }
 
-// Output parity and checkerboard site of this thread (block = one 64-site tile).
+// Output parity and checkerboard site of this thread (block = one 64-site
+// tile).  A launch over both parities gives consecutive blocks the even and
+// the odd tile of one region: each reads the links and spinors of the other,
+// so both are fetched into the same XCD's L2 once.
 __device__ __forceinline__ int64_t hop_site_index(const HopArgs &a, int lane, int &p, int64_t &blk) {
     blk = a.xcd ? xcd_block(blockIdx.x, gridDim.x) : (int64_t)blockIdx.x;
+    if (a.paired) {
+        p = (int)(blk & 1);
+        return brick_tile(a, blk >> 1) * HOP_SITES + lane;
+    }
     const int q = blk >= a.bpp ? 1 : 0;
     p = a.par0 ^ q;
     return brick_tile(a, blk - q * a.bpp) * HOP_SITES + lane;
@@ -234,40 +247,18 @@ static void launch_l(const HopArgs &a, bool dag, bool hasy, bool norm, dim3 grid
     else launch_p<P, LK, false>(a, hasy, norm, grid, st);
 }
 
-// Brick height for the blocked traversal (0 = plain order); needs whole
-// tiles per (z,t) plane.  See the rules next to LQCD_BRICK_MODE.
-static int brick_height(const Geom &g, int prec, int *plane_tiles) {
-    *plane_tiles = 0;
-    if (!LQCD_HOP_BRICK || !((LQCD_BRICK_PRECS >> prec) & 1)) return 0;
-    // small lattices live in the caches anyway, and there the extra index
-    // arithmetic and the loss of plain order cost more (16^4 FP32: 48% -> 40%)
-    if (g.vh < ((int64_t)1 << 18)) return 0;
-    const int64_t plane = (int64_t)g.lxh * g.L[1];
-    if (plane % TILE != 0 || g.vh % TILE != 0) return 0;
-    const int64_t pt = plane / TILE;
-    if (LQCD_BRICK_MODE == 1 && g.L[2] % 8 == 0 && g.L[2] > 8) {
-        *plane_tiles = (int)pt;
-        return g.L[2] / 8;
-    }
-    const int64_t slice_bytes = pt * spinor_tile_bytes(prec);
-    for (int bz = g.L[2] - 1; bz >= 1; --bz) {
-        if (g.L[2] % bz == 0 && 3 * bz * slice_bytes <= BRICK_L2_BUDGET) {
-            *plane_tiles = (int)pt;
-            return bz;
-        }
-    }
-    return 0;
-}
-
 int hop_launch(const HopArgs &a0, int prec, int link, bool dag, int nparity, hipStream_t st) {
     HopArgs a = a0;
     a.bpp = (a.g.vh + HOP_SITES - 1) / HOP_SITES;
     a.xcd = a.xcd && LQCD_HOP_XCD;
     a.bz = brick_height(a.g, prec, &a.plane_tiles);
+    a.paired = nparity == 2 && LQCD_HOP_PAIRED;
     const int64_t spinors = (int64_t)(nparity * half_spinor_bytes(a.g, prec));
     const int64_t links = (int64_t)gauge_bytes(a.g, prec, link);
     const bool out_nt = OUT_NT;
-    const bool link_nt = LQCD_LINK_NT && spinors + links > INFINITY_CACHE_BYTES;
+    // a both-parity launch reads every link twice (forward from its own site,
+    // backward from the paired tile), so it keeps them cached
+    const bool link_nt = LQCD_LINK_NT && !a.paired && spinors + links > INFINITY_CACHE_BYTES;
     a.stream = LQCD_HOP_STREAM >= 0 ? LQCD_HOP_STREAM : (out_nt ? 1 : 0) | (link_nt ? 2 : 0);
     dim3 grid((unsigned)(a.bpp * nparity));
     const bool hasy = a.y[0] != nullptr || a.y[1] != nullptr;

@@ -12,6 +12,11 @@
 
 namespace lqcd {
 
+// staged kernel shape (ablation switch: 0 = every wave reads every spinor)
+#ifndef LQCD_FORCE_STAGE
+#define LQCD_FORCE_STAGE 1
+#endif
+
 struct ForceArgs {
     Geom g;
     char *F;
@@ -20,6 +25,7 @@ struct ForceArgs {
     int64_t bpp;  // blocks per parity
     double coeff;
     int mode, accumulate;
+    int plane_tiles, bz;  // brick traversal (bz = 0: plain tile order)
 };
 
 template <typename T>
@@ -30,52 +36,51 @@ __device__ __forceinline__ void outer_add(cplx<T> w[9], const cplx<T> a[3], cons
         for (int j = 0; j < 3; ++j) w[3 * i + j] = w[3 * i + j] + cmul_conj(b[j], a[i]);
 }
 
-template <int MU, int P, int LK>
-__device__ __forceinline__ void force_direction(const ForceArgs &a, int p, int64_t s, const Coord &c) {
-    using T = typename real_of<P>::type;
-    const Geom &g = a.g;
-    int64_t fwd;
-    bool at_last;
+// Forward neighbour x + mu of site s (parity p) and whether the hop crosses
+// the last slice (where the boundary sign applies).
+template <int MU>
+__device__ __forceinline__ int64_t force_neighbour(const Geom &g, int64_t s, const Coord &c,
+                                                   bool &at_last) {
     if constexpr (MU == 0) {
         const int64_t row = s - (c.x >> 1);
         const int xp = c.x + 1 == g.L[0] ? 0 : c.x + 1;
-        fwd = row + (xp >> 1);
         at_last = c.x == g.L[0] - 1;
+        return row + (xp >> 1);
     } else {
         const int xm = MU == 1 ? c.y : MU == 2 ? c.z : c.t;
         const int L = g.L[MU];
         const int64_t st = MU == 1 ? g.sy : MU == 2 ? g.sz : g.st;
         at_last = xm == L - 1;
-        fwd = at_last ? s - (int64_t)(L - 1) * st : s + st;
+        return at_last ? s - (int64_t)(L - 1) * st : s + st;
     }
-    const double sgn = (at_last && g.bc[MU] < 0) ? -a.coeff : a.coeff;
-    const char *Xh = a.X + p * a.hb, *Yh = a.Y + p * a.hb;
-    const char *Xn = a.X + (p ^ 1) * a.hb, *Yn = a.Y + (p ^ 1) * a.hb;
+}
 
-    cplx<T> w[9];
+// W = X(x+mu) (x) ((1-g) Y(x))^dag + ((1+g) Y(x+mu)) (x) X(x)^dag from the
+// two neighbour spinors and the site's own X, Y.
+template <int MU, typename T>
+__device__ __forceinline__ void force_outer(const cplx<T> xn[12], const cplx<T> yn[12],
+                                            const cplx<T> xh[12], const cplx<T> yh[12], cplx<T> w[9]) {
+    cplx<T> a0[3], a1[3], b0[3], b1[3];
 #pragma unroll
     for (int k = 0; k < 9; ++k) w[k] = {0, 0};
-    {
-        // X(x+mu) (x) ((1-g) Y(x))^dag
-        cplx<T> v[12], hx0[3], hx1[3], hy0[3], hy1[3];
-        load_spinor<P>(Xn, fwd, v);
-        project_half<MU, -1>(v, hx0, hx1);
-        load_spinor<P>(Yh, s, v);
-        project_half<MU, -1>(v, hy0, hy1);
-        outer_add(w, hx0, hy0);
-        outer_add(w, hx1, hy1);
-    }
-    {
-        // ((1+g) Y(x+mu)) (x) X(x)^dag
-        cplx<T> v[12], hy0[3], hy1[3], hx0[3], hx1[3];
-        load_spinor<P>(Yn, fwd, v);
-        project_half<MU, 1>(v, hy0, hy1);
-        load_spinor<P>(Xh, s, v);
-        project_half<MU, 1>(v, hx0, hx1);
-        outer_add(w, hy0, hx0);
-        outer_add(w, hy1, hx1);
-    }
-    const T cs = (T)sgn;
+    project_half<MU, -1>(xn, a0, a1);
+    project_half<MU, -1>(yh, b0, b1);
+    outer_add(w, a0, b0);
+    outer_add(w, a1, b1);
+    project_half<MU, 1>(yn, a0, a1);
+    project_half<MU, 1>(xh, b0, b1);
+    outer_add(w, a0, b0);
+    outer_add(w, a1, b1);
+}
+
+// Scale W by the coefficient and boundary sign, form G = W^dag (mode 1) or
+// F = -TA(U W) (mode 0), optionally add the old output, store.
+template <int MU, int P, int LK>
+__device__ __forceinline__ void force_store(const ForceArgs &a, int p, int64_t s, bool flip,
+                                            cplx<typename real_of<P>::type> w[9]) {
+    using T = typename real_of<P>::type;
+    const Geom &g = a.g;
+    const T cs = (T)(flip ? -a.coeff : a.coeff);
 #pragma unroll
     for (int k = 0; k < 9; ++k) w[k] = scale(cs, w[k]);
 
@@ -114,10 +119,42 @@ __device__ __forceinline__ void force_direction(const ForceArgs &a, int p, int64
     store_link<P, 18, OUT_NT>(a.F, g.ntiles, p, s, MU, out);
 }
 
+// Link of direction MU at site s, every spinor read from memory.
+template <int MU, int P, int LK>
+__device__ __forceinline__ void force_direction(const ForceArgs &a, int p, int64_t s, const Coord &c) {
+    using T = typename real_of<P>::type;
+    bool at_last;
+    const int64_t fwd = force_neighbour<MU>(a.g, s, c, at_last);
+    cplx<T> w[9];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) w[k] = {0, 0};
+    {
+        // X(x+mu) (x) ((1-g) Y(x))^dag
+        cplx<T> v[12], a0[3], a1[3], b0[3], b1[3];
+        load_spinor<P>(a.X + (p ^ 1) * a.hb, fwd, v);
+        project_half<MU, -1>(v, a0, a1);
+        load_spinor<P>(a.Y + p * a.hb, s, v);
+        project_half<MU, -1>(v, b0, b1);
+        outer_add(w, a0, b0);
+        outer_add(w, a1, b1);
+    }
+    {
+        // ((1+g) Y(x+mu)) (x) X(x)^dag
+        cplx<T> v[12], a0[3], a1[3], b0[3], b1[3];
+        load_spinor<P>(a.Y + (p ^ 1) * a.hb, fwd, v);
+        project_half<MU, 1>(v, a0, a1);
+        load_spinor<P>(a.X + p * a.hb, s, v);
+        project_half<MU, 1>(v, b0, b1);
+        outer_add(w, a0, b0);
+        outer_add(w, a1, b1);
+    }
+    force_store<MU, P, LK>(a, p, s, at_last && a.g.bc[MU] < 0, w);
+}
+
 // One 64-site tile per block; wave w computes the link of direction w for
 // every site of the tile (each link is owned by exactly one thread).
 template <int P, int LK>
-__global__ __launch_bounds__(256) void force_k(ForceArgs a) {
+__global__ __launch_bounds__(256) void force_plain_k(ForceArgs a) {
     const int lane = threadIdx.x & 63;
     const int w = threadIdx.x >> 6;
     const int64_t blk = xcd_block(blockIdx.x, gridDim.x);
@@ -130,6 +167,92 @@ __global__ __launch_bounds__(256) void force_k(ForceArgs a) {
         case 1: force_direction<1, P, LK>(a, p, s, c); break;
         case 2: force_direction<2, P, LK>(a, p, s, c); break;
         default: force_direction<3, P, LK>(a, p, s, c); break;
+    }
+}
+
+// Spin rows 2h and 2h + 1 (complexes 6h .. 6h + 5) of the FP64 or FP32
+// spinor at site s: the words of one half of the site in the tile layout.
+template <int P>
+__device__ __forceinline__ void load_spinor_half(const char *__restrict__ base, int64_t s, int h,
+                                                 cplx<typename real_of<P>::type> v[6]) {
+    const int lane = (int)(s & (TILE - 1));
+    const char *t = base + (s >> TILE_SHIFT) * spinor_tile_bytes(P);
+    if constexpr (P == LQCD_F64) {
+        const v2d *w = reinterpret_cast<const v2d *>(t) + lane;
+#pragma unroll
+        for (int k = 0; k < 6; ++k) {
+            const v2d d = w[(6 * h + k) * TILE];
+            v[k] = {d.x, d.y};
+        }
+    } else {
+        const v4f *w = reinterpret_cast<const v4f *>(t) + lane;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            const v4f f = w[(3 * h + k) * TILE];
+            v[2 * k] = {f.x, f.y};
+            v[2 * k + 1] = {f.z, f.w};
+        }
+    }
+}
+
+template <int MU, int P, int LK>
+__device__ __forceinline__ void force_staged(const ForceArgs &a, int p, int64_t s, const Coord &c,
+                                             int lane, bool active,
+                                             const cplx<typename real_of<P>::type> (*xs)[64],
+                                             const cplx<typename real_of<P>::type> (*ys)[64]) {
+    using T = typename real_of<P>::type;
+    bool at_last = false;
+    cplx<T> xn[12], yn[12];
+    int64_t fwd = 0;
+    if (active) {
+        fwd = force_neighbour<MU>(a.g, s, c, at_last);
+        load_spinor<P>(a.X + (p ^ 1) * a.hb, fwd, xn);
+        load_spinor<P>(a.Y + (p ^ 1) * a.hb, fwd, yn);
+    }
+    __syncthreads();
+    if (!active) return;
+    cplx<T> xh[12], yh[12], w[9];
+#pragma unroll
+    for (int k = 0; k < 12; ++k) {
+        xh[k] = xs[k][lane];
+        yh[k] = ys[k][lane];
+    }
+    force_outer<MU>(xn, yn, xh, yh, w);
+    force_store<MU, P, LK>(a, p, s, at_last && a.g.bc[MU] < 0, w);
+}
+
+// Staged shape.  Consecutive blocks take the even and the odd tile of one
+// region (their neighbours are each other's sites, so both parities of X
+// and Y are fetched into the same XCD's L2), regions are walked in the hop
+// kernels' brick order, and the tile's own X and Y are loaded once by the
+// four waves together and read from LDS by all of them (every wave needs
+// them; the neighbour spinors are per direction).
+template <int P, int LK>
+__global__ __launch_bounds__(256) void force_k(ForceArgs a) {
+    using T = typename real_of<P>::type;
+    __shared__ cplx<T> xs[12][64], ys[12][64];
+    const int lane = threadIdx.x & 63;
+    const int w = threadIdx.x >> 6;
+    const int64_t blk = xcd_block(blockIdx.x, gridDim.x);
+    const int p = (int)(blk & 1);
+    const int64_t s = brick_order(blk >> 1, a.plane_tiles, a.bz, a.g.L[2], a.g.L[3]) * 64 + lane;
+    const bool active = s < a.g.vh;
+    if (active) {
+        // wave q stages spin rows 2(q & 1) and 2(q & 1) + 1 of X (q < 2) or Y
+        const char *src = (w < 2 ? a.X : a.Y) + p * a.hb;
+        cplx<T> v[6];
+        load_spinor_half<P>(src, s, w & 1, v);
+        cplx<T>(*dst)[64] = w < 2 ? xs : ys;
+        const int k0 = 6 * (w & 1);
+#pragma unroll
+        for (int k = 0; k < 6; ++k) dst[k0 + k][lane] = v[k];
+    }
+    const Coord c = active ? cb_coords(a.g, p, s) : Coord{};
+    switch (w) {
+        case 0: force_staged<0, P, LK>(a, p, s, c, lane, active, xs, ys); break;
+        case 1: force_staged<1, P, LK>(a, p, s, c, lane, active, xs, ys); break;
+        case 2: force_staged<2, P, LK>(a, p, s, c, lane, active, xs, ys); break;
+        default: force_staged<3, P, LK>(a, p, s, c, lane, active, xs, ys); break;
     }
 }
 
@@ -159,14 +282,19 @@ extern "C" int lqcd_fermion_force(const lqcd_geom_t *gg, void *F_out, const void
     a.mode = mode;
     a.accumulate = accumulate ? 1 : 0;
     a.bpp = (g.vh + 63) / 64;
+    a.bz = brick_height(g, prec, &a.plane_tiles);
     dim3 grid((unsigned)(2 * a.bpp)), block(256);
     hipStream_t st = (hipStream_t)stream;
+#define LQCD_FORCE(P, LK)                                                       \
+    if (LQCD_FORCE_STAGE) force_k<P, LK><<<grid, block, 0, st>>>(a);           \
+    else force_plain_k<P, LK><<<grid, block, 0, st>>>(a);
     if (prec == LQCD_F64) {
-        if (link == 18) force_k<LQCD_F64, 18><<<grid, block, 0, st>>>(a);
-        else force_k<LQCD_F64, 12><<<grid, block, 0, st>>>(a);
+        if (link == 18) { LQCD_FORCE(LQCD_F64, 18) }
+        else { LQCD_FORCE(LQCD_F64, 12) }
     } else {
-        if (link == 18) force_k<LQCD_F32, 18><<<grid, block, 0, st>>>(a);
-        else force_k<LQCD_F32, 12><<<grid, block, 0, st>>>(a);
+        if (link == 18) { LQCD_FORCE(LQCD_F32, 18) }
+        else { LQCD_FORCE(LQCD_F32, 12) }
     }
+#undef LQCD_FORCE
     return check_launch();
 }
