@@ -300,3 +300,35 @@ def test_full_size_sampled(dims, prec, link):
             want = dirac.dhop_at(DeviceGather(src), DeviceGather(Ur), sites, dagger=dag)
             got = res[sites[:, 3], sites[:, 2], sites[:, 1], sites[:, 0]].cpu().numpy()
             assert rel(got, want) < tol
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("dims", [(32, 32, 32, 32), (32, 32, 36, 16), (18, 18, 42, 40)])
+@pytest.mark.parametrize("prec,link", [(P.F64, 18), (P.F32, 12), (P.F16, 12)])
+def test_full_lattice_large_sampled(dims, prec, link):
+    """Both-parity D_hop (even and odd tiles paired in one launch, links kept
+    cached) and its adjoint on large lattices against the oracle at 256
+    sampled sites including every boundary corner."""
+    from tests.gpu_helpers import DeviceGather
+    lat = P.Lattice(dims)
+    Ud, psid = LI.workload_fields_device(6, dims, "cuda")
+    tdt = torch.complex64 if prec == P.F32 else torch.complex128
+    if prec == P.F32:
+        Ur, pr, tol = Ud.to(tdt).to(torch.complex128), psid.to(tdt).to(torch.complex128), TOL32
+    elif prec == P.F16:
+        Ur, pr, tol = Ud, psid, 5e-3  # against unrounded inputs: storage error only
+    else:
+        Ur, pr, tol = Ud, psid, TOL64
+    Uf = P.pack_gauge(lat, Ud.to(tdt), prec, link)
+    inp = P.pack_spinor(lat, psid.to(tdt), prec)
+    out = P.new_spinor(lat, prec, P.FULL)
+    rng = np.random.default_rng(14)
+    corners = np.array([[x, y, z, t] for x in (0, dims[0] - 1) for y in (0, dims[1] - 1)
+                        for z in (0, dims[2] - 1) for t in (0, dims[3] - 1)])
+    for dag in (False, True):
+        P.dslash(out, inp, Uf, dagger=dag)
+        res = P.unpack_spinor(out)
+        sites = np.concatenate([corners, np.stack([rng.integers(0, d, 240) for d in dims], 1)])
+        want = dirac.dhop_at(DeviceGather(pr), DeviceGather(Ur), sites, dagger=dag)
+        got = res[sites[:, 3], sites[:, 2], sites[:, 1], sites[:, 0]].cpu().numpy()
+        assert rel(got, want) < tol

@@ -234,6 +234,44 @@ def test_solve_and_force_48x3x96():
     assert rel(got, want) < 2e-6
 
 
+# Large lattices reach the force kernel's traversal orders: 32^4 (z-slab
+# bricks), 32x32x36x16 (bricks sized by the L2 budget) and 18x18x42x40
+# (plain order, ragged last tile).
+@pytest.mark.slow
+@pytest.mark.parametrize("dims", [(32, 32, 32, 32), (32, 32, 36, 16), (18, 18, 42, 40)])
+@pytest.mark.parametrize("prec,link", [(P.F64, 18), (P.F32, 12)])
+def test_force_large_sampled(dims, prec, link):
+    """Force and raw gradient on large lattices against the oracle's link
+    formula at 128 sampled links, including links that cross the last slice
+    in every direction (FP64 arithmetic on the stored inputs)."""
+    from tests.gpu_helpers import DeviceGather
+    lat = P.Lattice(dims)
+    Ud, Xd = LI.workload_fields_device(40, dims, "cuda")
+    _, Yd = LI.workload_fields_device(41, dims, "cuda")
+    tdt = torch.complex64 if prec == P.F32 else torch.complex128
+    Uf = P.pack_gauge(lat, Ud.to(tdt), prec, link)
+    Xf = P.pack_spinor(lat, Xd.to(tdt), prec)
+    Yf = P.pack_spinor(lat, Yd.to(tdt), prec)
+    c0 = 0.29
+    G = P.fermion_force(Xf, Yf, Uf, c0, mode=1)
+    F = P.fermion_force(Xf, Yf, Uf, c0, mode=0)
+    Xc, Yc = P.unpack_spinor(Xf), P.unpack_spinor(Yf)
+    Uc = P.unpack_gauge(Uf)  # the links the kernel sees (row 2 rebuilt)
+    rng = np.random.default_rng(13)
+    picked = np.stack([rng.integers(0, d, 128) for d in dims] + [rng.integers(0, 4, 128)], 1)
+    for mu in range(4):
+        picked[mu] = [d - 1 for d in dims] + [mu]
+        picked[4 + mu] = [0, 0, 0, 0, mu]
+    want_g = force.link_gradient_at(DeviceGather(Xc), DeviceGather(Yc), None, c0, picked)
+    idx = tuple(torch.as_tensor(picked[:, k]) for k in (3, 2, 1, 0, 4))
+    want_f = force.su3_force_at(want_g, Uc[idx].cpu().numpy().astype(np.complex128))
+    tol = 2e-6 if prec == P.F32 else 1e-13
+    got_g = P.unpack_gauge(G)[idx].cpu().numpy().astype(np.complex128)
+    got_f = P.unpack_gauge(F)[idx].cpu().numpy().astype(np.complex128)
+    assert rel(got_g, want_g) < tol
+    assert rel(got_f, want_f) < tol
+
+
 @pytest.mark.parametrize("inner", [(P.F64, 18), (P.F32, 12)])
 def test_normal_solve_vjp_vs_oracle(inner):
     """Gradients through the solve (adjoint solve + force kernel) against
