@@ -178,11 +178,11 @@ __device__ __forceinline__ void hop_chi(const cplx<T> psi[12], const cplx<T> u[9
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
         if constexpr (UDAG) {
-            x0[a] = cmul_conj(u[a], h0[0]) + cmul_conj(u[3 + a], h0[1]) + cmul_conj(u[6 + a], h0[2]);
-            x1[a] = cmul_conj(u[a], h1[0]) + cmul_conj(u[3 + a], h1[1]) + cmul_conj(u[6 + a], h1[2]);
+            x0[a] = cdot3c(u[a], h0[0], u[3 + a], h0[1], u[6 + a], h0[2]);
+            x1[a] = cdot3c(u[a], h1[0], u[3 + a], h1[1], u[6 + a], h1[2]);
         } else {
-            x0[a] = u[3 * a] * h0[0] + u[3 * a + 1] * h0[1] + u[3 * a + 2] * h0[2];
-            x1[a] = u[3 * a] * h1[0] + u[3 * a + 1] * h1[1] + u[3 * a + 2] * h1[2];
+            x0[a] = cdot3(u[3 * a], h0[0], u[3 * a + 1], h0[1], u[3 * a + 2], h0[2]);
+            x1[a] = cdot3(u[3 * a], h1[0], u[3 * a + 1], h1[1], u[3 * a + 2], h1[2]);
         }
     }
 }

@@ -98,6 +98,63 @@ __device__ __forceinline__ cplx<T> cmul_conj(cplx<T> a, cplx<T> b) {
 template <typename T>
 __device__ __forceinline__ T norm2(cplx<T> a) { return a.re * a.re + a.im * a.im; }
 
+template <typename T>
+__device__ __forceinline__ T fmad(T a, T b, T c) {
+    if constexpr (sizeof(T) == 8) return __builtin_fma(a, b, c);
+    else return __builtin_fmaf(a, b, c);
+}
+
+// a0 b0 + a1 b1 + a2 b2 as two chains of fused multiply-adds (one product
+// and five FMAs per component; the operator form costs two more additions
+// per term).
+template <typename T>
+__device__ __forceinline__ cplx<T> cdot3(cplx<T> a0, cplx<T> b0, cplx<T> a1, cplx<T> b1,
+                                         cplx<T> a2, cplx<T> b2) {
+    T re = a0.re * b0.re, im = a0.re * b0.im;
+    re = fmad(-a0.im, b0.im, re);
+    im = fmad(a0.im, b0.re, im);
+    re = fmad(a1.re, b1.re, re);
+    im = fmad(a1.re, b1.im, im);
+    re = fmad(-a1.im, b1.im, re);
+    im = fmad(a1.im, b1.re, im);
+    re = fmad(a2.re, b2.re, re);
+    im = fmad(a2.re, b2.im, im);
+    re = fmad(-a2.im, b2.im, re);
+    im = fmad(a2.im, b2.re, im);
+    return {re, im};
+}
+
+// conj(a0) b0 + conj(a1) b1 + conj(a2) b2, the same way.
+template <typename T>
+__device__ __forceinline__ cplx<T> cdot3c(cplx<T> a0, cplx<T> b0, cplx<T> a1, cplx<T> b1,
+                                          cplx<T> a2, cplx<T> b2) {
+    T re = a0.re * b0.re, im = a0.re * b0.im;
+    re = fmad(a0.im, b0.im, re);
+    im = fmad(-a0.im, b0.re, im);
+    re = fmad(a1.re, b1.re, re);
+    im = fmad(a1.re, b1.im, im);
+    re = fmad(a1.im, b1.im, re);
+    im = fmad(-a1.im, b1.re, im);
+    re = fmad(a2.re, b2.re, re);
+    im = fmad(a2.re, b2.im, im);
+    re = fmad(a2.im, b2.im, re);
+    im = fmad(-a2.im, b2.re, im);
+    return {re, im};
+}
+
+// conj(a b - c d) with fused multiply-adds.
+template <typename T>
+__device__ __forceinline__ cplx<T> conj_cross(cplx<T> a, cplx<T> b, cplx<T> c, cplx<T> d) {
+    T re = a.re * b.re, im = -(a.re * b.im);
+    re = fmad(-a.im, b.im, re);
+    im = fmad(-a.im, b.re, im);
+    re = fmad(-c.re, d.re, re);
+    im = fmad(c.re, d.im, im);
+    re = fmad(c.im, d.im, re);
+    im = fmad(c.im, d.re, im);
+    return {re, im};
+}
+
 // Multiply by one of {1, -1, i, -i}, coded as 0, 1, 2, 3.
 template <int C, typename T>
 __device__ __forceinline__ cplx<T> mul_unit(cplx<T> a) {
@@ -288,9 +345,9 @@ __device__ __forceinline__ void store_spinor(char *__restrict__ base, int64_t s,
 // Row 2 of an SU(3) matrix from rows 0 and 1: conj(row0 x row1).
 template <typename T>
 __device__ __forceinline__ void reconstruct_row2(cplx<T> u[9]) {
-    u[6] = conj(u[1] * u[5] - u[2] * u[4]);
-    u[7] = conj(u[2] * u[3] - u[0] * u[5]);
-    u[8] = conj(u[0] * u[4] - u[1] * u[3]);
+    u[6] = conj_cross(u[1], u[5], u[2], u[4]);
+    u[7] = conj_cross(u[2], u[3], u[0], u[5]);
+    u[8] = conj_cross(u[0], u[4], u[1], u[3]);
 }
 
 // Address of the link tile of direction mu for parity p and site tile `tile`.
