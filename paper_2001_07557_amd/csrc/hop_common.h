@@ -161,19 +161,36 @@ __device__ __forceinline__ void project_half(const cplx<T> psi[12], cplx<T> h0[3
     }
 }
 
+// a + k b for a unit k (code as for mul_unit) in the arithmetic type T, from
+// inputs of element type E, as fused multiply-adds by +-one (exact).  With
+// binary16 inputs each component is one mixed-precision FMA that reads the
+// stored halves directly; `one` must then be a register value the compiler
+// cannot see is 1, or it turns the FMA back into an addition of two
+// converted values.
+template <int K, typename T, typename E>
+__device__ __forceinline__ cplx<T> add_unit(cplx<E> a, cplx<E> b, T one) {
+    const T ar = (T)a.re, ai = (T)a.im, br = (T)b.re, bi = (T)b.im;
+    if constexpr (K == 0) return {fmad(br, one, ar), fmad(bi, one, ai)};
+    else if constexpr (K == 1) return {fmad(br, -one, ar), fmad(bi, -one, ai)};
+    else if constexpr (K == 2) return {fmad(bi, -one, ar), fmad(br, one, ai)};
+    else return {fmad(bi, one, ar), fmad(br, -one, ai)};
+}
+
 // Project with (1 + S g_mu), apply the boundary sign and multiply by U (or
 // U^dag): the two colour vectors chi0, chi1 of one hop.
-template <int MU, int S, bool UDAG, typename T>
-__device__ __forceinline__ void hop_chi(const cplx<T> psi[12], const cplx<T> u[9], T sign,
+template <int MU, int S, bool UDAG, typename T, typename E>
+__device__ __forceinline__ void hop_chi(const cplx<E> psi[12], const cplx<T> u[9], T sign,
                                         cplx<T> x0[3], cplx<T> x1[3]) {
     using PR = Proj<MU>;
     constexpr int k0 = S > 0 ? PR::c0 : neg_code(PR::c0);
     constexpr int k1 = S > 0 ? PR::c1 : neg_code(PR::c1);
+    T one = 1;
+    if constexpr (sizeof(E) == 2) asm volatile("" : "+v"(one));
     cplx<T> h0[3], h1[3];
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-        h0[c] = scale(sign, psi[c] + mul_unit<k0>(psi[PR::a0 * 3 + c]));
-        h1[c] = scale(sign, psi[3 + c] + mul_unit<k1>(psi[PR::a1 * 3 + c]));
+        h0[c] = scale(sign, add_unit<k0, T>(psi[c], psi[PR::a0 * 3 + c], one));
+        h1[c] = scale(sign, add_unit<k1, T>(psi[3 + c], psi[PR::a1 * 3 + c], one));
     }
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
@@ -201,15 +218,6 @@ __device__ __forceinline__ void chi_accumulate(const cplx<T> x0[3], const cplx<T
         acc[PR::a0 * 3 + a] = acc[PR::a0 * 3 + a] + mul_unit<r0>(x0[a]);
         acc[PR::a1 * 3 + a] = acc[PR::a1 * 3 + a] + mul_unit<r1>(x1[a]);
     }
-}
-
-// Project, multiply by U (or U^dag) and accumulate one hop into acc.
-template <int MU, int S, bool UDAG, typename T>
-__device__ __forceinline__ void hop_accumulate(const cplx<T> psi[12], const cplx<T> u[9], T sign,
-                                               cplx<T> acc[12]) {
-    cplx<T> x0[3], x1[3];
-    hop_chi<MU, S, UDAG>(psi, u, sign, x0, x1);
-    chi_accumulate<MU, S>(x0, x1, acc);
 }
 
 // Neighbour index and boundary sign of one hop (FWD: x + mu, else x - mu).
@@ -250,7 +258,8 @@ __device__ __forceinline__ void hop_single(const Geom &g, const char *__restrict
     constexpr int S = FWD ? (DAG ? 1 : -1) : (DAG ? -1 : 1);
     bool flip;
     const int64_t nb = hop_neighbour<MU, FWD>(g, s, c, flip);
-    cplx<T> psi[12], u[9];
+    cplx<typename hop_elem<P>::type> psi[12];
+    cplx<T> u[9];
     T sgn = flip ? T(-1) : T(1);
     load_spinor_hop<P>(in, nb, psi, sgn);
     if constexpr (FWD) load_link<P, LK, LNT>(U, g.ntiles, p, s, MU, u);
@@ -286,7 +295,8 @@ __device__ __forceinline__ void hop_direction(const Geom &g, const char *__restr
     cplx<T> f[6];
     {
         T sgn = flip_f ? T(-1) : T(1);
-        cplx<T> psi[12], u[9];
+        cplx<typename hop_elem<P>::type> psi[12];
+        cplx<T> u[9];
         load_spinor_hop<P>(in, fwd, psi, sgn);
         load_link<P, LK, LNT>(U, g.ntiles, p, s, MU, u);
         hop_chi<MU, SF, false>(psi, u, sgn, f, f + 3);
@@ -294,7 +304,8 @@ __device__ __forceinline__ void hop_direction(const Geom &g, const char *__restr
     hop_fence<T, 6>(f);
     {
         T sgn = flip_b ? T(-1) : T(1);
-        cplx<T> psi[12], u[9], b[6];
+        cplx<typename hop_elem<P>::type> psi[12];
+        cplx<T> u[9], b[6];
         load_spinor_hop<P>(in, bwd, psi, sgn);
         load_link<P, LK, LNT>(U, g.ntiles, p ^ 1, bwd, MU, u);
         hop_chi<MU, SB, true>(psi, u, sgn, b, b + 3);

@@ -257,12 +257,19 @@ __device__ __forceinline__ void load_spinor(const char *__restrict__ base, int64
     }
 }
 
+// Element type a hop reads spinors in: the arithmetic type, except binary16
+// storage, whose values stay binary16 until the projection (which adds them
+// with mixed-precision fused multiply-adds, so no separate conversion runs).
+template <int P> struct hop_elem { using type = typename real_of<P>::type; };
+template <> struct hop_elem<LQCD_F16> { using type = _Float16; };
+typedef _Float16 v2h __attribute__((ext_vector_type(2)));
+
 // Load for a hop: binary16 storage returns the stored (unscaled) values and
 // multiplies `factor` by the site's scale, which the hop then applies to the
 // projected half-spinor (12 products instead of 24).
 template <int P>
 __device__ __forceinline__ void load_spinor_hop(const char *__restrict__ base, int64_t s,
-                                                cplx<typename real_of<P>::type> v[12],
+                                                cplx<typename hop_elem<P>::type> v[12],
                                                 typename real_of<P>::type &factor) {
     if constexpr (P == LQCD_F16) {
         const int64_t tile = s >> TILE_SHIFT;
@@ -276,9 +283,8 @@ __device__ __forceinline__ void load_spinor_hop(const char *__restrict__ base, i
             uint32_t u[4] = {q.x, q.y, q.z, q.w};
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
-                __half2 h = *reinterpret_cast<__half2 *>(&u[j]);
-                float2 f = __half22float2(h);
-                v[4 * k + j] = {f.x, f.y};
+                const v2h h = __builtin_bit_cast(v2h, u[j]);
+                v[4 * k + j] = {h.x, h.y};
             }
         }
     } else {
