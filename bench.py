@@ -157,7 +157,7 @@ def main():
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py: this build measures the hot path on one GPU only; "
+        print("bench.py: the library runs on one GPU only; "
               "the multi-GPU halo exchange is a design, not an implementation (use --gpus 1)",
               file=sys.stderr)
         sys.exit(2)

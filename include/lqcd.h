@@ -1,10 +1,10 @@
 /*
  * lqcd.h - C ABI of the MI355X Wilson-Dirac library (liblqcd.so).
  *
- * The operator is the Wilson hopping term that the paper applies on KNL in
- * Sec. 3.3 (Fig. 4d) and calls "the generic version of the Wilson kernel";
- * the paper does not write it out, so the definitions below are the textbook
- * ones, stated in full:
+ * The operator is the Wilson hopping term whose generic (not hand-unrolled)
+ * kernel the paper times on KNL in Sec. 3.3 (Fig. 4d); the paper does not
+ * write it out, so the definitions below are the textbook ones, stated in
+ * full:
  *
  *   (D_hop psi)(x) = sum_{mu=0..3} [ s+_mu(x) (1 - g_mu) U_mu(x) psi(x+mu)
  *                                  + s-_mu(x) (1 + g_mu) U_mu(x-mu)^dag psi(x-mu) ]
@@ -265,9 +265,9 @@ int lqcd_fermion_force(const lqcd_geom_t *g, void *F_out, const void *X, const v
 
 /* Shift of a full spinor field: out(x) = s in(x + dir mu_hat), dir = +1 or
    -1, with s = bc[mu] when the step wraps around the lattice (from the last
-   slice for dir = +1, the first for dir = -1) and 1 otherwise.  The stencil
-   building block of Sec. 3.1 ("shift and stencil operations"); with one site
-   per lane it needs no lane rearrangement.  out must not alias in.  All
+   slice for dir = +1, the first for dir = -1) and 1 otherwise.  The shift
+   that the stencils of Sec. 3.1 are built from; with one site per lane it
+   needs no lane rearrangement.  out must not alias in.  All
    precisions; binary16 fields are copied exactly (the sign rides on the
    site scale). */
 int lqcd_cshift(const lqcd_geom_t *g, void *out, const void *in, int mu, int dir, int prec,

@@ -7,7 +7,7 @@ shares no code with the GPU path: it works on the canonical (lexicographic,
 x fastest) arrays with explicit 4x4 gamma matrices and full 3x3 links, in
 complex128, with numpy primitives (roll, einsum, matmul) as its only helpers.
 
-The paper (Sec. 3.3, Fig. 4d) applies "the Wilson Dirac operator" but never
+The paper (Sec. 3.3, Fig. 4d) times the Wilson Dirac operator but never
 writes it down; every definition below is the textbook Wilson hopping term in
 the conventions listed in each module, and each function is pinned by the
 CPU tests against facts fixed by the mathematics (plane-wave eigenvalues of

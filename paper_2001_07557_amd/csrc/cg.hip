@@ -167,7 +167,7 @@ __global__ __launch_bounds__(CG_BLOCK) void cg_residual_k(char *r, const char *b
 }
 
 // ---------------------------------------------------------------------------
-// host driver
+// host side of the solver
 // ---------------------------------------------------------------------------
 
 struct CGWork {

@@ -1,7 +1,7 @@
 // Lattice SU(3) matrix product W_mu(x) = op(U_mu(x)) op(V_mu(x)) for all 4V
-// links (op = identity or hermitian conjugate): the "custom SU(3)
-// matrix-matrix multiplication" the paper benchmarks on the vector engine
-// (Sec. 3.3, Fig. 4a-c).  Pure streaming: 198 flop per link against three
+// links (op = identity or hermitian conjugate): the per-link SU(3) matrix
+// product whose hand-written kernel the paper benchmarks on the vector
+// engine (Sec. 3.3, Fig. 4a-c).  Pure streaming: 198 flop per link against three
 // links of traffic, one thread per link, a block = one 64-site tile with
 // wave w on direction w.  12-real storage rebuilds row 2 of the inputs and
 // stores rows 0 and 1 of the product (the product of SU(3) matrices is SU(3)).
