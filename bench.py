@@ -11,7 +11,8 @@ reported under "variants".  The solve of the 32^4 smoothed-link system
 (FP64 CG vs mixed FP32 / binary16 inner solvers to a 1e-10 true residual) is
 reported under "cg", the 48^3x96 solve plus force under "solve_force", the
 paper's building blocks under "building_blocks".  "sweep" repeats the hop
-timing on 24^4, 32^4 and 48^3x96, and on the benchmark lattice with a
+timing on 24^4, 32^4, 48^3x96 and 48^3x12 (one GPU's share of 48^3x96 split
+eight ways in t), and on the benchmark lattice with a
 rotating pool of input copies larger than the Infinity Cache, each also as a
 fraction of a measured copy bandwidth; "grad" times the differentiated
 operator (forward M psi, backward M^dag g and link force) on 24^4.
@@ -354,8 +355,9 @@ def run_sweep(P, LI, torch, lattice, dev, apps=20, steps=5, warmup=2):
     copy = copy_bandwidth(P, torch)
     torch.cuda.empty_cache()
     out = {"copy": copy, "apps_per_step": apps, "steps": steps}
+    # 48^3x12 is one GPU's share of 48^3x96 split eight ways in t
     cases = [(lattice, "pool")] + [(d, "plain") for d in ((24, 24, 24, 24), (32, 32, 32, 32),
-                                                           (48, 48, 48, 96))]
+                                                           (48, 48, 48, 96), (48, 48, 48, 12))]
     for dims, kind in cases:
         U, psi = LI.workload_fields_device(1, dims, dev)
         lat = P.Lattice(dims)
