@@ -53,13 +53,19 @@ def dims_of(field) -> tuple:
 
 
 def shift(field: np.ndarray, mu: int, s: int) -> np.ndarray:
-    """field(x + s mu_hat), periodic wrap (boundary signs applied separately)."""
+    """field(x + s mu_hat), periodic wrap (boundary signs applied separately).
+
+    Shifts of Sec. 3.1 (the building block of the paper's stencils).
+    """
     return np.roll(field, -s, axis=3 - mu)
 
 
 def cshift(field: np.ndarray, mu: int, s: int, bc=DEFAULT_BC) -> np.ndarray:
     """out(x) = field(x + s mu_hat) times bc_mu when the step crosses the
-    boundary (s = +1 from the last slice, s = -1 from the first)."""
+    boundary (s = +1 from the last slice, s = -1 from the first).
+
+    Shifts of Sec. 3.1 (the building block of the paper's stencils).
+    """
     dims = dims_of(field)
     out = shift(field, mu, s)
     edge = dims[mu] - 1 if s > 0 else 0
@@ -76,12 +82,20 @@ def coord(dims: Sequence[int], mu: int) -> np.ndarray:
 
 
 def sign_fwd(dims, bc, mu) -> np.ndarray:
-    """s+_mu(x): bc_mu on the last slice in direction mu, 1 elsewhere."""
+    """s+_mu(x): bc_mu on the last slice in direction mu, 1 elsewhere.
+
+    Operator timed in Sec. 3.3 (Fig. 4d); the paper gives no formula, so this
+    is the textbook definition in the conventions of this module's header.
+    """
     return np.where(coord(dims, mu) == dims[mu] - 1, float(bc[mu]), 1.0)
 
 
 def sign_bwd(dims, bc, mu) -> np.ndarray:
-    """s-_mu(x): bc_mu on the first slice in direction mu, 1 elsewhere."""
+    """s-_mu(x): bc_mu on the first slice in direction mu, 1 elsewhere.
+
+    Operator timed in Sec. 3.3 (Fig. 4d); the paper gives no formula, so this
+    is the textbook definition in the conventions of this module's header.
+    """
     return np.where(coord(dims, mu) == 0, float(bc[mu]), 1.0)
 
 
@@ -100,7 +114,11 @@ def dagger3(u: np.ndarray) -> np.ndarray:
 
 
 def dhop(psi: np.ndarray, U: np.ndarray, bc=DEFAULT_BC, dagger: bool = False) -> np.ndarray:
-    """D_hop psi (or D_hop^dag psi) on the full lattice."""
+    """D_hop psi (or D_hop^dag psi) on the full lattice.
+
+    Operator timed in Sec. 3.3 (Fig. 4d); the paper gives no formula, so this
+    is the textbook definition in the conventions of this module's header.
+    """
     dims = dims_of(psi)
     out = np.zeros_like(psi)
     sg = -1.0 if dagger else 1.0
@@ -117,7 +135,11 @@ def dhop(psi: np.ndarray, U: np.ndarray, bc=DEFAULT_BC, dagger: bool = False) ->
 
 
 def wilson(psi, U, kappa, bc=DEFAULT_BC, dagger=False):
-    """M psi = psi - kappa D_hop psi (M^dag with dagger=True)."""
+    """M psi = psi - kappa D_hop psi (M^dag with dagger=True).
+
+    Operator timed in Sec. 3.3 (Fig. 4d); the paper gives no formula, so this
+    is the textbook definition in the conventions of this module's header.
+    """
     return psi - kappa * dhop(psi, U, bc, dagger)
 
 
@@ -132,24 +154,40 @@ def odd_mask(dims) -> np.ndarray:
 
 
 def project(psi: np.ndarray, parity: int) -> np.ndarray:
-    """P_parity psi: keep the sites of the given parity, zero the others."""
+    """P_parity psi: keep the sites of the given parity, zero the others.
+
+    Operator timed in Sec. 3.3 (Fig. 4d); the paper gives no formula, so this
+    is the textbook definition in the conventions of this module's header.
+    """
     m = odd_mask(dims_of(psi))
     keep = m if parity == 1 else ~m
     return psi * keep[..., None, None]
 
 
 def meo(psi_o, U, bc=DEFAULT_BC, dagger=False):
-    """Even rows, odd columns of D_hop (or of D_hop^dag)."""
+    """Even rows, odd columns of D_hop (or of D_hop^dag).
+
+    Operator timed in Sec. 3.3 (Fig. 4d); the paper gives no formula, so this
+    is the textbook definition in the conventions of this module's header.
+    """
     return project(dhop(project(psi_o, 1), U, bc, dagger), 0)
 
 
 def moe(psi_e, U, bc=DEFAULT_BC, dagger=False):
-    """Odd rows, even columns of D_hop (or of D_hop^dag)."""
+    """Odd rows, even columns of D_hop (or of D_hop^dag).
+
+    Operator timed in Sec. 3.3 (Fig. 4d); the paper gives no formula, so this
+    is the textbook definition in the conventions of this module's header.
+    """
     return project(dhop(project(psi_e, 0), U, bc, dagger), 1)
 
 
 def mhat(x_e, U, kappa, bc=DEFAULT_BC):
-    """Schur operator on even sites: x_e - kappa^2 D_eo D_oe x_e."""
+    """Schur operator on even sites: x_e - kappa^2 D_eo D_oe x_e.
+
+    Operator timed in Sec. 3.3 (Fig. 4d); the paper gives no formula, so this
+    is the textbook definition in the conventions of this module's header.
+    """
     return project(x_e, 0) - kappa ** 2 * meo(moe(x_e, U, bc), U, bc)
 
 
@@ -158,12 +196,19 @@ def mhat_dag(x_e, U, kappa, bc=DEFAULT_BC):
 
     (D_eo)^dag is the odd-even block of D_hop^dag and (D_oe)^dag its even-odd
     block.
+
+    Operator timed in Sec. 3.3 (Fig. 4d); the paper gives no formula, so this
+    is the textbook definition in the conventions of this module's header.
     """
     return project(x_e, 0) - kappa ** 2 * meo(moe(x_e, U, bc, True), U, bc, True)
 
 
 def normal_op(x_e, U, kappa, bc=DEFAULT_BC):
-    """A x_e = Mhat^dag Mhat x_e (hermitian positive definite)."""
+    """A x_e = Mhat^dag Mhat x_e (hermitian positive definite).
+
+    Operator timed in Sec. 3.3 (Fig. 4d); the paper gives no formula, so this
+    is the textbook definition in the conventions of this module's header.
+    """
     return mhat_dag(mhat(x_e, U, kappa, bc), U, kappa, bc)
 
 
@@ -176,6 +221,9 @@ def dhop_at(psi, U, sites: np.ndarray, bc=DEFAULT_BC, dagger=False) -> np.ndarra
 
     Returns an array [n][4][3].  Neighbour coordinates wrap modulo L_mu and
     pick up bc_mu when the hop crosses the boundary.
+
+    Operator timed in Sec. 3.3 (Fig. 4d); the paper gives no formula, so this
+    is the textbook definition in the conventions of this module's header.
     """
     dims = dims_of(psi)
     sites = np.asarray(sites, dtype=np.int64)

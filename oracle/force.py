@@ -29,12 +29,20 @@ from . import dirac, solver
 
 
 def outer_spin_sum(a: np.ndarray, b: np.ndarray) -> np.ndarray:
-    """sum_s a_{s,i} conj(b_{s,j}) -> [..][3][3]."""
+    """sum_s a_{s,i} conj(b_{s,j}) -> [..][3][3].
+
+    The paper does not treat derivatives; textbook definition in the
+    conventions of this module's header.
+    """
     return np.einsum("...si,...sj->...ij", a, np.conj(b))
 
 
 def link_gradient(X, Y, U, c0, bc=dirac.DEFAULT_BC) -> np.ndarray:
-    """Raw gradient G_mu(x) = W_mu(x)^dag of c0 Re(Y^dag D_hop X) w.r.t. U."""
+    """Raw gradient G_mu(x) = W_mu(x)^dag of c0 Re(Y^dag D_hop X) w.r.t. U.
+
+    The paper does not treat derivatives; textbook definition in the
+    conventions of this module's header.
+    """
     dims = dirac.dims_of(X)
     G = np.zeros_like(U)
     for mu in range(4):
@@ -48,42 +56,70 @@ def link_gradient(X, Y, U, c0, bc=dirac.DEFAULT_BC) -> np.ndarray:
 
 
 def traceless_antihermitian(a: np.ndarray) -> np.ndarray:
+    """
+    The paper does not treat derivatives; textbook definition in the
+    conventions of this module's header.
+    """
     d = 0.5 * (a - dirac.dagger3(a))
     tr = np.trace(d, axis1=-2, axis2=-1)
     return d - (tr / 3.0)[..., None, None] * np.eye(3)
 
 
 def su3_force(G, U) -> np.ndarray:
-    """F_mu(x) = TA(G_mu(x) U_mu(x)^dag)."""
+    """F_mu(x) = TA(G_mu(x) U_mu(x)^dag).
+
+    The paper does not treat derivatives; textbook definition in the
+    conventions of this module's header.
+    """
     return traceless_antihermitian(G @ dirac.dagger3(U))
 
 
 def action_norm(psi, U, kappa, bc=dirac.DEFAULT_BC) -> float:
-    """S = sum_x |(M psi)(x)|^2."""
+    """S = sum_x |(M psi)(x)|^2.
+
+    The paper does not treat derivatives; textbook definition in the
+    conventions of this module's header.
+    """
     phi = dirac.wilson(psi, U, kappa, bc)
     return float(np.vdot(phi.ravel(), phi.ravel()).real)
 
 
 def grad_psi_norm(psi, U, kappa, bc=dirac.DEFAULT_BC) -> np.ndarray:
-    """dS/dpsi for S = |M psi|^2: 2 M^dag M psi."""
+    """dS/dpsi for S = |M psi|^2: 2 M^dag M psi.
+
+    The paper does not treat derivatives; textbook definition in the
+    conventions of this module's header.
+    """
     return 2.0 * dirac.wilson(dirac.wilson(psi, U, kappa, bc), U, kappa, bc, dagger=True)
 
 
 def grad_links_norm(psi, U, kappa, bc=dirac.DEFAULT_BC) -> np.ndarray:
-    """dS/dU for S = |M psi|^2 (raw complex gradient, PyTorch convention)."""
+    """dS/dU for S = |M psi|^2 (raw complex gradient, PyTorch convention).
+
+    The paper does not treat derivatives; textbook definition in the
+    conventions of this module's header.
+    """
     phi = dirac.wilson(psi, U, kappa, bc)
     return link_gradient(psi, phi, U, -2.0 * kappa, bc)
 
 
 def vjp(psi, U, kappa, g, bc=dirac.DEFAULT_BC):
-    """Vector-Jacobian product of phi = M psi for an upstream gradient g."""
+    """Vector-Jacobian product of phi = M psi for an upstream gradient g.
+
+    The paper does not treat derivatives; textbook definition in the
+    conventions of this module's header.
+    """
     gpsi = dirac.wilson(g, U, kappa, bc, dagger=True)
     gU = link_gradient(psi, g, U, -kappa, bc)
     return gpsi, gU
 
 
 def pseudofermion_fields(x_e, U, kappa, bc=dirac.DEFAULT_BC):
-    """(X, Y) on the full lattice for S = phi_e^dag (Mhat^dag Mhat)^-1 phi_e."""
+    """(X, Y) on the full lattice for S = phi_e^dag (Mhat^dag Mhat)^-1 phi_e.
+
+    The paper does not treat derivatives; textbook definition in the
+    conventions of this module's header.
+    """
     x_o = dirac.moe(x_e, U, bc)
     y_e = dirac.mhat(x_e, U, kappa, bc)
     y_o = dirac.moe(y_e, U, bc, dagger=True)
@@ -91,7 +127,11 @@ def pseudofermion_fields(x_e, U, kappa, bc=dirac.DEFAULT_BC):
 
 
 def pseudofermion_force(x_e, U, kappa, bc=dirac.DEFAULT_BC):
-    """su(3) force of the pseudofermion action given its solution X_e."""
+    """su(3) force of the pseudofermion action given its solution X_e.
+
+    The paper does not treat derivatives; textbook definition in the
+    conventions of this module's header.
+    """
     X, Y = pseudofermion_fields(x_e, U, kappa, bc)
     return su3_force(link_gradient(X, Y, U, 2.0 * kappa ** 2, bc), U)
 
@@ -101,6 +141,9 @@ def link_gradient_at(X, Y, U, c0, links, bc=dirac.DEFAULT_BC) -> np.ndarray:
 
     Same definition as :func:`link_gradient`, evaluated link by link from
     the fields at x and x + mu (for fields too large to shift whole).
+
+    The paper does not treat derivatives; textbook definition in the
+    conventions of this module's header.
     """
     dims = dirac.dims_of(X)
     links = np.asarray(links, dtype=np.int64)
@@ -130,7 +173,11 @@ def link_gradient_at(X, Y, U, c0, links, bc=dirac.DEFAULT_BC) -> np.ndarray:
 
 
 def su3_force_at(G, U_links) -> np.ndarray:
-    """TA(G U^dag) for gathered links ([n][3][3] each)."""
+    """TA(G U^dag) for gathered links ([n][3][3] each).
+
+    The paper does not treat derivatives; textbook definition in the
+    conventions of this module's header.
+    """
     return traceless_antihermitian(G @ dirac.dagger3(U_links))
 
 
@@ -150,6 +197,9 @@ def normal_solve_vjp(x_e, g_e, U, kappa, bc=dirac.DEFAULT_BC, tol=1e-13):
     X(b) = (b, D_oe b), Y(a) = (a, (D_eo)^dag a), so
     dL = kappa^2 [Re(Y(Mhat x)^dag dD X(lambda)) + Re(Y(Mhat lambda)^dag dD X(x))].
     Returns (lambda, raw link gradient G).
+
+    The paper does not treat derivatives; textbook definition in the
+    conventions of this module's header.
     """
     lam, _, _ = solver.solve_normal(g_e, U, kappa, bc, tol=tol)
     X1, _ = _xy_fields(lam, U, bc)

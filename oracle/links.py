@@ -17,10 +17,18 @@ import numpy as np
 
 
 def compress(U: np.ndarray) -> np.ndarray:
+    """
+    The paper does not treat link compression; the standard 12-real form of an
+    SU(3) matrix (third row from unitarity and det U = 1).
+    """
     return U[..., :2, :].copy()
 
 
 def reconstruct(rows01: np.ndarray) -> np.ndarray:
+    """
+    The paper does not treat link compression; the standard 12-real form of an
+    SU(3) matrix (third row from unitarity and det U = 1).
+    """
     a = rows01[..., 0, :]
     b = rows01[..., 1, :]
     c = np.conj(np.stack([a[..., 1] * b[..., 2] - a[..., 2] * b[..., 1],
@@ -30,11 +38,19 @@ def reconstruct(rows01: np.ndarray) -> np.ndarray:
 
 
 def round_f32(z: np.ndarray) -> np.ndarray:
-    """Round a complex128 array to complex64 and back (FP32 storage)."""
+    """Round a complex128 array to complex64 and back (FP32 storage).
+
+    Storage rounding of the reduced-precision variants; the paper does not
+    treat reduced precision.
+    """
     return z.astype(np.complex64).astype(np.complex128)
 
 
 def round_f16_links(z: np.ndarray) -> np.ndarray:
+    """
+    Storage rounding of the reduced-precision variants; the paper does not
+    treat reduced precision.
+    """
     re = z.real.astype(np.float16).astype(np.float64)
     im = z.imag.astype(np.float16).astype(np.float64)
     return re + 1j * im
@@ -46,6 +62,9 @@ def round_f16_spinor(psi: np.ndarray) -> np.ndarray:
     scale = max |real| over the site's 24 reals (FP32); stored value =
     binary16(real * r) with r = 1/scale rounded to FP32 and the product in
     FP32; the value seen by the arithmetic is stored * scale (FP32).
+
+    Storage rounding of the reduced-precision variants; the paper does not
+    treat reduced precision.
     """
     re = psi.real.astype(np.float32)
     im = psi.imag.astype(np.float32)
@@ -63,6 +82,8 @@ def su3_product(U: np.ndarray, V: np.ndarray, adj_u: bool = False, adj_v: bool =
 
     The lattice SU(3) matrix product of the paper's Fig. 4a-c, written with
     the library matrix product.
+
+    The per-link SU(3) matrix product of Sec. 3.3 (Fig. 4a-c).
     """
     a = np.conj(np.swapaxes(U, -1, -2)) if adj_u else U
     b = np.conj(np.swapaxes(V, -1, -2)) if adj_v else V

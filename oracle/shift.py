@@ -13,7 +13,10 @@ import numpy as np
 
 
 def split_rotate(v: np.ndarray, s: int, r: int) -> np.ndarray:
-    """Rotate each of the s contiguous blocks of the last axis left by r."""
+    """Rotate each of the s contiguous blocks of the last axis left by r.
+
+    Sec. 3.1, the lane permutation defined there.
+    """
     vl = v.shape[-1]
     if s <= 0 or vl % s:
         raise ValueError("split count must divide the vector length")

@@ -28,7 +28,11 @@ def norm2(a: np.ndarray) -> float:
 
 
 def cg(apply_a, b, tol=1e-10, maxiter=10000, x0=None):
-    """Plain CG; returns (x, iterations, true relative residual)."""
+    """Plain CG; returns (x, iterations, true relative residual).
+
+    The paper does not treat solvers; textbook Hestenes-Stiefel CG on the
+    normal system of the Sec. 3.3 operator.
+    """
     x = np.zeros_like(b) if x0 is None else x0.copy()
     r = b - apply_a(x) if x0 is not None else b.copy()
     p = r.copy()
@@ -58,13 +62,21 @@ def cg(apply_a, b, tol=1e-10, maxiter=10000, x0=None):
 
 
 def solve_normal(b_e, U, kappa, bc=dirac.DEFAULT_BC, tol=1e-10, maxiter=10000, x0=None):
-    """Solve Mhat^dag Mhat x_e = b_e on even sites."""
+    """Solve Mhat^dag Mhat x_e = b_e on even sites.
+
+    The paper does not treat solvers; textbook Hestenes-Stiefel CG on the
+    normal system of the Sec. 3.3 operator.
+    """
     return cg(lambda v: dirac.normal_op(v, U, kappa, bc), dirac.project(b_e, 0),
               tol=tol, maxiter=maxiter, x0=x0)
 
 
 def true_residual(x_e, b_e, U, kappa, bc=dirac.DEFAULT_BC) -> float:
-    """||b_e - Mhat^dag Mhat x_e|| / ||b_e||, FP64."""
+    """||b_e - Mhat^dag Mhat x_e|| / ||b_e||, FP64.
+
+    The paper does not treat solvers; textbook Hestenes-Stiefel CG on the
+    normal system of the Sec. 3.3 operator.
+    """
     b = dirac.project(b_e, 0)
     return float(np.sqrt(norm2(b - dirac.normal_op(x_e, U, kappa, bc)) / norm2(b)))
 
@@ -73,6 +85,9 @@ def full_solution(b, U, kappa, bc=dirac.DEFAULT_BC, tol=1e-12, maxiter=10000):
     """Solve M x = b on the full lattice through the Schur complement.
 
     Mhat x_e = c_e is solved as Mhat^dag Mhat x_e = Mhat^dag c_e.
+
+    The paper does not treat solvers; textbook Hestenes-Stiefel CG on the
+    normal system of the Sec. 3.3 operator.
     """
     b_e = dirac.project(b, 0)
     b_o = dirac.project(b, 1)
