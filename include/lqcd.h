@@ -123,7 +123,8 @@ size_t lqcd_gauge_bytes(const lqcd_geom_t *g, int prec, int link);
 /* layout conversion (untimed set-up work)                                 */
 /* ---------------------------------------------------------------------- */
 
-/* Canonical spinor -> internal.  src is a full canonical array; for subset
+/* Layout conversion has no passage in the paper (the layouts are this
+   library's).  Canonical spinor -> internal.  src is a full canonical array; for subset
    EVEN/ODD only that parity is read and dst is a half field.  Values are
    rounded to `prec` (F16: per-site scale, see LQCD_F16). */
 int lqcd_pack_spinor(const lqcd_geom_t *g, void *dst, const void *src_canon,
@@ -147,7 +148,8 @@ int lqcd_unpack_gauge(const lqcd_geom_t *g, void *dst_canon, const void *src,
 /* the operator                                                            */
 /* ---------------------------------------------------------------------- */
 
-/* Full lattice:  out = alpha * D_hop in + beta * y   (y may be NULL: beta
+/* The operator of Sec. 3.3 (Fig. 4d), as defined at the top of this header.
+   Full lattice:  out = alpha * D_hop in + beta * y   (y may be NULL: beta
    ignored).  M = 1 - kappa D_hop is alpha = -kappa, beta = 1, y = in.
    out, in, y: full spinor fields of precision prec; U: gauge field of
    (prec, link).  out must not alias in; it may alias y. */
@@ -181,7 +183,9 @@ int lqcd_mhat(const lqcd_geom_t *g, void *out_e, const void *in_e, void *tmp_o,
 /* BLAS-1 with deterministic wavefront reductions                          */
 /* ---------------------------------------------------------------------- */
 
-/* Bytes of device workspace a reduction over `subset` needs. */
+/* Inner products and vector updates of the solver (the paper has no solver;
+   these are the plain definitions).
+   Bytes of device workspace a reduction over `subset` needs. */
 size_t lqcd_reduce_workspace_bytes(const lqcd_geom_t *g, int subset);
 
 /* result[0] + i result[1] = <a, b> = sum conj(a) b over every site of the
@@ -212,7 +216,10 @@ int lqcd_convert(const lqcd_geom_t *g, int subset, void *dst, int dst_prec,
 /* Bytes of workspace lqcd_cg_solve needs for the given inner precision. */
 size_t lqcd_cg_workspace_bytes(const lqcd_geom_t *g, int inner_prec, int inner_link);
 
-/* Solve A x = b on even sites, A = Mhat^dag Mhat, by CG with reliable updates.
+/* The paper has no solver: Hestenes-Stiefel CG on the normal system of the
+ * Sec. 3.3 operator, with FP64 reliable updates around a reduced-precision
+ * inner iteration.
+ * Solve A x = b on even sites, A = Mhat^dag Mhat, by CG with reliable updates.
  *   x_e:   FP64 even half field; in: initial guess, out: solution.
  *   b_e:   FP64 even half field (right-hand side).
  *   U_hi:  FP64 gauge field (link_hi reals), used for the reliable updates
@@ -244,8 +251,9 @@ int lqcd_cg_solve(const lqcd_geom_t *g, void *x_e, const void *b_e,
 /* differentiation                                                         */
 /* ---------------------------------------------------------------------- */
 
-/* Link derivative of c0 * Re(Y^dag D_hop X) for every link (owner computes,
- * no atomics).  With
+/* The paper has no derivatives: the textbook link derivative of the Sec. 3.3
+ * operator.  Link derivative of coeff * Re(Y^dag D_hop X) for every link (owner
+ * computes, no atomics).  With
  *   W_mu(x) = coeff * s+_mu(x) [ X(x+mu) (x) ((1-g_mu) Y(x))^dag
  *                              + ((1+g_mu) Y(x+mu)) (x) X(x)^dag ],
  * (a (x) b^dag)_ij = sum_spin a_{s,i} conj(b_{s,j}), the result written is
