@@ -585,6 +585,62 @@ def test_split_rotate_pins():
     assert np.array_equal(split_rotate(reals, 4, 2 * 3).view(np.complex128), split_rotate(z, 4, 3))
 
 
+def _to_lanes(F, n):
+    """Full lattice array F (axis k = dimension d-1-k, dimension 0 fastest)
+    in the layout of Sec. 3.1: dimension i of length L_i is cut into n_i
+    blocks of O_i = L_i / n_i sites; the sites o + b O of one sublattice
+    share a vector, lane sum_i b_i stride_i with stride_0 = 1."""
+    d = F.ndim
+    L = [F.shape[d - 1 - i] for i in range(d)]
+    O = [L[i] // n[i] for i in range(d)]
+    nl = int(np.prod(n))
+    out = np.empty(tuple(O[d - 1 - k] for k in range(d)) + (nl,), dtype=F.dtype)
+    for lane in range(nl):
+        b, rem = [], lane
+        for i in range(d):
+            b.append(rem % n[i])
+            rem //= n[i]
+        idx = tuple(slice(b[d - 1 - k] * O[d - 1 - k], (b[d - 1 - k] + 1) * O[d - 1 - k])
+                    for k in range(d))
+        out[..., lane] = F[idx]
+    return out
+
+
+@pytest.mark.parametrize("dims,n", [((8, 4), (4, 2)), ((4, 8), (2, 4)), ((8, 8, 8), (4, 4, 4)),
+                                    ((4, 8, 8), (2, 4, 4)), ((8, 4, 6), (4, 2, 3))])
+def test_split_rotate_is_the_lattice_shift(dims, n):
+    """What the lane permutation is for (Sec. 3.1): shifting a lattice stored
+    with sublattice vectors.  Shift the full lattice by one site in direction
+    mu (np.roll, independent of the oracle), store both fields in the vector
+    layout, and compare: away from the sublattice edge a shift copies whole
+    vectors; on the edge the vector is the neighbour's vector permuted by
+    split_rotate with s = prod_{i>mu} n_i blocks and r = prod_{i<mu} n_i lanes."""
+    from oracle.shift import split_rotate
+    d = len(dims)
+    rng = np.random.default_rng(27)
+    F = rng.standard_normal(tuple(dims[d - 1 - k] for k in range(d)))
+    Fv = _to_lanes(F, n)
+    for mu in range(d):
+        axis = d - 1 - mu
+        G = np.roll(F, -1, axis=axis)          # G(x) = F(x + mu)
+        Gv = _to_lanes(G, n)
+        O_mu = dims[mu] // n[mu]
+        s = int(np.prod(n[mu + 1:]))
+        r = int(np.prod(n[:mu]))
+        for o in range(O_mu):
+            take = [slice(None)] * d
+            take[axis] = o
+            got = Gv[tuple(take)]
+            if o < O_mu - 1:
+                src = [slice(None)] * d
+                src[axis] = o + 1
+                assert np.array_equal(got, Fv[tuple(src)])
+            else:
+                src = [slice(None)] * d
+                src[axis] = 0
+                assert np.array_equal(got, split_rotate(Fv[tuple(src)], s, r))
+
+
 def test_su3_product_pins():
     U, _ = LI.workload_fields(23, (2, 2, 2, 2))
     V, _ = LI.workload_fields(24, (2, 2, 2, 2))
