@@ -80,10 +80,8 @@ def round_f16_spinor(psi: np.ndarray) -> np.ndarray:
 def su3_product(U: np.ndarray, V: np.ndarray, adj_u: bool = False, adj_v: bool = False) -> np.ndarray:
     """W = op(U) op(V) link by link (op = identity or hermitian conjugate).
 
-    The lattice SU(3) matrix product of the paper's Fig. 4a-c, written with
+    The per-link SU(3) matrix product of Sec. 3.3 (Fig. 4a-c), written with
     the library matrix product.
-
-    The per-link SU(3) matrix product of Sec. 3.3 (Fig. 4a-c).
     """
     a = np.conj(np.swapaxes(U, -1, -2)) if adj_u else U
     b = np.conj(np.swapaxes(V, -1, -2)) if adj_v else V

@@ -655,6 +655,11 @@ def test_su3_product_pins():
     assert np.abs(LI.det3(W) - 1).max() < 1e-14
     eye = links.su3_product(U, U, adj_u=True)
     assert np.abs(eye - np.eye(3)).max() < 1e-14
+    # the second dagger: U U^dag = 1, and U^dag V^dag = (V U)^dag
+    assert np.abs(links.su3_product(U, U, adj_v=True) - np.eye(3)).max() < 1e-14
+    vu = links.su3_product(V, U)
+    both = links.su3_product(U, V, adj_u=True, adj_v=True)
+    assert np.abs(both - np.conj(np.swapaxes(vu, -1, -2))).max() < 1e-14
 
 
 def test_normal_solve_vjp_finite_differences():
