@@ -56,7 +56,8 @@ def link_gradient(X, Y, U, c0, bc=dirac.DEFAULT_BC) -> np.ndarray:
 
 
 def traceless_antihermitian(a: np.ndarray) -> np.ndarray:
-    """
+    """TA(A) = (A - A^dag)/2 - tr(A - A^dag)/6 * 1.
+
     The paper does not treat derivatives; textbook definition in the
     conventions of this module's header.
     """

@@ -17,7 +17,8 @@ import numpy as np
 
 
 def compress(U: np.ndarray) -> np.ndarray:
-    """
+    """Rows 0 and 1 of each link (12 reals).
+
     The paper does not treat link compression; the standard 12-real form of an
     SU(3) matrix (third row from unitarity and det U = 1).
     """
@@ -25,7 +26,8 @@ def compress(U: np.ndarray) -> np.ndarray:
 
 
 def reconstruct(rows01: np.ndarray) -> np.ndarray:
-    """
+    """Full 3x3 links from rows 0 and 1: row 2 = conj(row0 x row1).
+
     The paper does not treat link compression; the standard 12-real form of an
     SU(3) matrix (third row from unitarity and det U = 1).
     """
@@ -47,7 +49,8 @@ def round_f32(z: np.ndarray) -> np.ndarray:
 
 
 def round_f16_links(z: np.ndarray) -> np.ndarray:
-    """
+    """Links rounded to IEEE binary16 entry by entry and back.
+
     Storage rounding of the reduced-precision variants; the paper does not
     treat reduced precision.
     """
