@@ -37,6 +37,10 @@ namespace lqcd {
 #ifndef LQCD_HOP_STREAM
 #define LQCD_HOP_STREAM -1
 #endif
+// row-parallel rebuild of the FP32 hop on small lattices (ablation switch)
+#ifndef LQCD_HOP_ROWS
+#define LQCD_HOP_ROWS 1
+#endif
 // both-parity launches pair the even and odd tile of a region (ablation switch)
 #ifndef LQCD_HOP_PAIRED
 #define LQCD_HOP_PAIRED 1
@@ -147,10 +151,57 @@ __device__ __forceinline__ void add_staged(const cplx<typename real_of<P>::type>
     chi_accumulate<H / 2, HopSign<H, DAG>::value>(x0, x1, acc);
 }
 
+// Spin row R of the output from the eight staged half-spinors: every hop
+// adds its chi0 to row 0, its chi1 to row 1 and a unit times one of them to
+// row a0 or a1 of its direction.
+template <int R, int H, int P, bool DAG>
+__device__ __forceinline__ void row_staged(const cplx<typename real_of<P>::type> (*chi)[6][64],
+                                           int lane, cplx<typename real_of<P>::type> row[3]) {
+    using PR = Proj<H / 2>;
+    constexpr int S = HopSign<H, DAG>::value;
+    constexpr int r0 = S > 0 ? conj_code(PR::c0) : neg_code(conj_code(PR::c0));
+    constexpr int r1 = S > 0 ? conj_code(PR::c1) : neg_code(conj_code(PR::c1));
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        if constexpr (R == 0) row[a] = row[a] + chi[H][a][lane];
+        else if constexpr (R == 1) row[a] = row[a] + chi[H][3 + a][lane];
+        else if constexpr (R == PR::a0) row[a] = row[a] + mul_unit<r0>(chi[H][a][lane]);
+        else row[a] = row[a] + mul_unit<r1>(chi[H][3 + a][lane]);
+    }
+}
+
+// Row-parallel rebuild (FP32 storage, out = alpha D in): wave R builds and
+// stores spin row R, i.e. complexes 3R .. 3R + 2 of the site, which straddle
+// the 16-byte words of the tile, so they are stored as three 8-byte halves.
+template <int R, int P, bool DAG, bool NT>
+__device__ __forceinline__ void rebuild_row(const HopArgs &a, int p, int64_t s,
+                                            const cplx<typename real_of<P>::type> (*chi)[6][64],
+                                            int lane) {
+    static_assert(P == LQCD_F32, "row stores assume the FP32 tile layout");
+    using T = typename real_of<P>::type;
+    cplx<T> row[3] = {{0, 0}, {0, 0}, {0, 0}};
+    row_staged<R, 0, P, DAG>(chi, lane, row);
+    row_staged<R, 1, P, DAG>(chi, lane, row);
+    row_staged<R, 2, P, DAG>(chi, lane, row);
+    row_staged<R, 3, P, DAG>(chi, lane, row);
+    row_staged<R, 4, P, DAG>(chi, lane, row);
+    row_staged<R, 5, P, DAG>(chi, lane, row);
+    row_staged<R, 6, P, DAG>(chi, lane, row);
+    row_staged<R, 7, P, DAG>(chi, lane, row);
+    const T alpha = (T)a.alpha;
+    char *t = a.out[p] + (s >> TILE_SHIFT) * spinor_tile_bytes(P) + (s & (TILE - 1)) * WORD;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const int c = 3 * R + k;
+        v2f *d = reinterpret_cast<v2f *>(t + (c / 2) * TILE * WORD + (c % 2) * 8);
+        put<NT>(d, v2f{alpha * row[k].re, alpha * row[k].im});
+    }
+}
+
 // 8-way shape: wave w computes hop w (direction w/2, forward for even w) and
 // stages the two colour vectors of its multiplied half-spinor in LDS; wave 0
 // rebuilds the four spin rows from the eight staged half-spinors.
-template <int P, int LK, bool DAG, bool HASY, bool NORM, int NTM>
+template <int P, int LK, bool DAG, bool HASY, bool NORM, int NTM, bool ROWS>
 __global__ __launch_bounds__(512) void hop8_kernel(HopArgs a) {
     using T = typename real_of<P>::type;
     __shared__ cplx<T> chi[8][6][64];
@@ -181,6 +232,19 @@ __global__ __launch_bounds__(512) void hop8_kernel(HopArgs a) {
         }
     }
     __syncthreads();
+    if constexpr (ROWS) {
+        static_assert(!HASY && !NORM, "the row-parallel rebuild has no y term and no norm");
+        if (active) {
+            switch (w) {
+                case 0: rebuild_row<0, P, DAG, (NTM & 1) != 0>(a, p, s, chi, lane); break;
+                case 1: rebuild_row<1, P, DAG, (NTM & 1) != 0>(a, p, s, chi, lane); break;
+                case 2: rebuild_row<2, P, DAG, (NTM & 1) != 0>(a, p, s, chi, lane); break;
+                case 3: rebuild_row<3, P, DAG, (NTM & 1) != 0>(a, p, s, chi, lane); break;
+                default: break;
+            }
+        }
+        return;
+    }
     double nrm[1] = {0.0};
     if (w == 0 && active) {
         cplx<T> acc[12];
@@ -213,8 +277,17 @@ constexpr int hop_shape(int prec) {
 
 template <int P, int LK, bool DAG, bool HASY, bool NORM, int NTM>
 static void launch_nt(const HopArgs &a, dim3 grid, hipStream_t st) {
-    if constexpr (hop_shape(P) == 8) hop8_kernel<P, LK, DAG, HASY, NORM, NTM><<<grid, 512, 0, st>>>(a);
-    else hop4_kernel<P, LK, DAG, HASY, NORM, NTM><<<grid, 256, 0, st>>>(a);
+    if constexpr (hop_shape(P) == 8) {
+        if constexpr (P == LQCD_F32 && !HASY && !NORM) {
+            if (a.rows) {
+                hop8_kernel<P, LK, DAG, HASY, NORM, NTM, true><<<grid, 512, 0, st>>>(a);
+                return;
+            }
+        }
+        hop8_kernel<P, LK, DAG, HASY, NORM, NTM, false><<<grid, 512, 0, st>>>(a);
+    } else {
+        hop4_kernel<P, LK, DAG, HASY, NORM, NTM><<<grid, 256, 0, st>>>(a);
+    }
 }
 
 // The cache hints are template arguments: a run-time choice between two
@@ -253,6 +326,10 @@ int hop_launch(const HopArgs &a0, int prec, int link, bool dag, int nparity, hip
     a.xcd = a.xcd && LQCD_HOP_XCD;
     a.bz = brick_height(a.g, prec, &a.plane_tiles);
     a.paired = nparity == 2 && LQCD_HOP_PAIRED;
+    // row-parallel rebuild where a launch is latency-bound (cache-resident
+    // lattices; on large ones the single-wave rebuild is a point faster)
+    a.rows = LQCD_HOP_ROWS && a.g.vh < ((int64_t)1 << 18) && a.y[0] == nullptr &&
+             a.y[1] == nullptr && a.partial == nullptr;
     const int64_t spinors = (int64_t)(nparity * half_spinor_bytes(a.g, prec));
     const int64_t links = (int64_t)gauge_bytes(a.g, prec, link);
     const bool out_nt = OUT_NT;

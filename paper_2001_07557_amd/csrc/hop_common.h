@@ -83,6 +83,7 @@ struct HopArgs {
     int plane_tiles, bz;
     int stream;           // non-temporal hints: bit 0 output stores, bit 1 link loads
     int paired;           // both parities: block 2i / 2i + 1 = even / odd tile i
+    int rows;             // 8-way shape: waves 0-3 rebuild one spin row each
 };
 
 // Tile visited by logical block b (within one parity).  With bricks of bz

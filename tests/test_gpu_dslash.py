@@ -96,6 +96,12 @@ def test_full_dslash_fp32(dims, bc, link):
         got = host(P.unpack_spinor(out))
         assert rel(got, dirac.wilson(psi32, U32, KAPPA, bc, dagger=dag)) < TOL32
         assert rel(got, dirac.wilson(psi, U, KAPPA, bc, dagger=dag)) < TOL32
+        # alpha D_hop alone (no y term: on small lattices the spin rows are
+        # rebuilt by four waves in parallel)
+        P.dslash(out, pf, Uf, alpha=-0.7, dagger=dag)
+        want = -0.7 * dirac.dhop(psi32, U32 if link == 18 else links.reconstruct(links.compress(U32)),
+                                 bc, dagger=dag)
+        assert rel(host(P.unpack_spinor(out)), want) < TOL32
 
 
 def eo_case(prec, link, dims=(16, 16, 16, 16), k=5):
