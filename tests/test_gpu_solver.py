@@ -157,13 +157,17 @@ def test_cg_zero_rhs_and_nan():
 def test_cg_32x4_smoothed_mixed_vs_fp64():
     """The 32^4 smoothed-link solve: FP64, FP32-12 and FP16-12 inner solvers
     all reach a 1e-10 true residual; residuals are recomputed here through
-    the Schur-operator entry point in FP64 and the solutions agree."""
+    the Schur-operator entry point in FP64 and by the FP64 oracle on the host
+    (same links and right-hand side), and the solutions agree."""
     dims = (32, 32, 32, 32)
     lat = P.Lattice(dims)
     Ud, psid = LI.workload_fields_device(3, dims, "cuda")
     Ud = LI.ape_smooth(Ud, steps=10, alpha=0.5)
     U_hi = P.pack_gauge(lat, Ud, P.F64, 18)
     b = P.pack_spinor(lat, psid, P.F64, P.EVEN)
+    U_host = host(Ud)
+    b_host = dirac.project(host(psid), 0)
+    bb = np.vdot(b_host, b_host).real
     sols = {}
     for name, (prec, link) in {"f64": (P.F64, 18), "f32": (P.F32, 12), "f16": (P.F16, 12)}.items():
         U_lo = U_hi if prec == P.F64 else P.pack_gauge(
@@ -182,5 +186,8 @@ def test_cg_32x4_smoothed_mixed_vs_fp64():
         res = np.sqrt(P.norm2(t2) / P.norm2(b))
         assert res <= 1.0001e-10
         sols[name] = host(P.unpack_spinor(x))
+        # the oracle's true residual of every solution
+        r = b_host - dirac.normal_op(sols[name], U_host, KAPPA)
+        assert np.sqrt(np.vdot(r, r).real / bb) <= 1.0001e-10
     for name in ("f32", "f16"):
         assert rel(sols[name], sols["f64"]) < 1e-7
