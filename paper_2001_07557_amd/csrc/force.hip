@@ -55,24 +55,6 @@ __device__ __forceinline__ int64_t force_neighbour(const Geom &g, int64_t s, con
     }
 }
 
-// W = X(x+mu) (x) ((1-g) Y(x))^dag + ((1+g) Y(x+mu)) (x) X(x)^dag from the
-// two neighbour spinors and the site's own X, Y.
-template <int MU, typename T>
-__device__ __forceinline__ void force_outer(const cplx<T> xn[12], const cplx<T> yn[12],
-                                            const cplx<T> xh[12], const cplx<T> yh[12], cplx<T> w[9]) {
-    cplx<T> a0[3], a1[3], b0[3], b1[3];
-#pragma unroll
-    for (int k = 0; k < 9; ++k) w[k] = {0, 0};
-    project_half<MU, -1>(xn, a0, a1);
-    project_half<MU, -1>(yh, b0, b1);
-    outer_add(w, a0, b0);
-    outer_add(w, a1, b1);
-    project_half<MU, 1>(yn, a0, a1);
-    project_half<MU, 1>(xh, b0, b1);
-    outer_add(w, a0, b0);
-    outer_add(w, a1, b1);
-}
-
 // Scale W by the coefficient and boundary sign, form G = W^dag (mode 1) or
 // F = -TA(U W) (mode 0), optionally add the old output, store.
 template <int MU, int P, int LK>
@@ -195,30 +177,48 @@ __device__ __forceinline__ void load_spinor_half(const char *__restrict__ base, 
     }
 }
 
+// Neighbour spinors of direction MU, read and projected to the halves that
+// enter the link's W; returns whether the link carries the boundary sign.
+template <int MU, int P>
+__device__ __forceinline__ bool force_neighbours(const ForceArgs &a, int p, int64_t s,
+                                                 cplx<typename real_of<P>::type> hx[6],
+                                                 cplx<typename real_of<P>::type> hy[6]) {
+    using T = typename real_of<P>::type;
+    bool at_last;
+    const int64_t fwd = force_neighbour<MU>(a.g, s, cb_coords(a.g, p, s), at_last);
+    cplx<T> v[12];
+    load_spinor<P>(a.X + (p ^ 1) * a.hb, fwd, v);
+    project_half<MU, -1>(v, hx, hx + 3);
+    load_spinor<P>(a.Y + (p ^ 1) * a.hb, fwd, v);
+    project_half<MU, 1>(v, hy, hy + 3);
+    return at_last && a.g.bc[MU] < 0;
+}
+
+// The link of direction MU at site s: W = X(x+mu) (x) ((1-g) Y(x))^dag +
+// ((1+g) Y(x+mu)) (x) X(x)^dag from the projected neighbour halves
+// hx = h[(1-g) X(x+mu)], hy = h[(1+g) Y(x+mu)] and the site's own Y, then X,
+// read from the block's LDS copy one at a time (fewer live registers).
 template <int MU, int P, int LK>
-__device__ __forceinline__ void force_staged(const ForceArgs &a, int p, int64_t s, const Coord &c,
-                                             int lane, bool active,
+__device__ __forceinline__ void force_staged(const ForceArgs &a, int p, int64_t s, int lane, bool flip,
+                                             const cplx<typename real_of<P>::type> hx[6],
+                                             const cplx<typename real_of<P>::type> hy[6],
                                              const cplx<typename real_of<P>::type> (*xs)[64],
                                              const cplx<typename real_of<P>::type> (*ys)[64]) {
     using T = typename real_of<P>::type;
-    bool at_last = false;
-    cplx<T> xn[12], yn[12];
-    int64_t fwd = 0;
-    if (active) {
-        fwd = force_neighbour<MU>(a.g, s, c, at_last);
-        load_spinor<P>(a.X + (p ^ 1) * a.hb, fwd, xn);
-        load_spinor<P>(a.Y + (p ^ 1) * a.hb, fwd, yn);
-    }
-    __syncthreads();
-    if (!active) return;
-    cplx<T> xh[12], yh[12], w[9];
+    cplx<T> v[12], b0[3], b1[3], w[9];
 #pragma unroll
-    for (int k = 0; k < 12; ++k) {
-        xh[k] = xs[k][lane];
-        yh[k] = ys[k][lane];
-    }
-    force_outer<MU>(xn, yn, xh, yh, w);
-    force_store<MU, P, LK>(a, p, s, at_last && a.g.bc[MU] < 0, w);
+    for (int k = 0; k < 9; ++k) w[k] = {0, 0};
+#pragma unroll
+    for (int k = 0; k < 12; ++k) v[k] = ys[k][lane];
+    project_half<MU, -1>(v, b0, b1);
+    outer_add(w, hx, b0);
+    outer_add(w, hx + 3, b1);
+#pragma unroll
+    for (int k = 0; k < 12; ++k) v[k] = xs[k][lane];
+    project_half<MU, 1>(v, b0, b1);
+    outer_add(w, hy, b0);
+    outer_add(w, hy + 3, b1);
+    force_store<MU, P, LK>(a, p, s, flip, w);
 }
 
 // Staged shape.  Consecutive blocks take the even and the odd tile of one
@@ -247,12 +247,26 @@ __global__ __launch_bounds__(256) void force_k(ForceArgs a) {
 #pragma unroll
         for (int k = 0; k < 6; ++k) dst[k0 + k][lane] = v[k];
     }
-    const Coord c = active ? cb_coords(a.g, p, s) : Coord{};
+    // each wave reads and projects the neighbours of its own direction while
+    // the staged words arrive; the branch rejoins before the barrier, which
+    // every thread of the block reaches
+    cplx<T> hx[6], hy[6];
+    bool flip = false;
+    if (active) {
+        switch (w) {
+            case 0: flip = force_neighbours<0, P>(a, p, s, hx, hy); break;
+            case 1: flip = force_neighbours<1, P>(a, p, s, hx, hy); break;
+            case 2: flip = force_neighbours<2, P>(a, p, s, hx, hy); break;
+            default: flip = force_neighbours<3, P>(a, p, s, hx, hy); break;
+        }
+    }
+    __syncthreads();
+    if (!active) return;
     switch (w) {
-        case 0: force_staged<0, P, LK>(a, p, s, c, lane, active, xs, ys); break;
-        case 1: force_staged<1, P, LK>(a, p, s, c, lane, active, xs, ys); break;
-        case 2: force_staged<2, P, LK>(a, p, s, c, lane, active, xs, ys); break;
-        default: force_staged<3, P, LK>(a, p, s, c, lane, active, xs, ys); break;
+        case 0: force_staged<0, P, LK>(a, p, s, lane, flip, hx, hy, xs, ys); break;
+        case 1: force_staged<1, P, LK>(a, p, s, lane, flip, hx, hy, xs, ys); break;
+        case 2: force_staged<2, P, LK>(a, p, s, lane, flip, hx, hy, xs, ys); break;
+        default: force_staged<3, P, LK>(a, p, s, lane, flip, hx, hy, xs, ys); break;
     }
 }
 
