@@ -231,7 +231,6 @@ struct Solver {
         a.alpha = alpha;
         a.beta = 1.0;
         a.par0 = out_par;
-        a.xcd = 1;
         a.out[out_par] = out;
         a.in[out_par] = in;
         a.y[out_par] = y;

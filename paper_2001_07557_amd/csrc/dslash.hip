@@ -80,14 +80,15 @@ __device__ __forceinline__ double hop_epilogue(const HopArgs &a, int p, int64_t 
 // the odd tile of one region: each reads the links and spinors of the other,
 // so both are fetched into the same XCD's L2 once.
 __device__ __forceinline__ int64_t hop_site_index(const HopArgs &a, int lane, int &p, int64_t &blk) {
-    blk = a.xcd ? xcd_block(blockIdx.x, gridDim.x) : (int64_t)blockIdx.x;
-    if (a.paired) {
-        p = (int)(blk & 1);
-        return brick_tile(a, blk >> 1) * HOP_SITES + lane;
-    }
+    // selects, not branches: every launch argument is read up front
+    const uint32_t bx = blockIdx.x;
+    blk = LQCD_HOP_XCD ? xcd_block(bx, a.nblk) : (int64_t)bx;
+    // paired: blocks 2i / 2i + 1 take the even / odd tile i; otherwise the
+    // first bpp blocks take parity par0 and the rest the other parity
     const int q = blk >= a.bpp ? 1 : 0;
-    p = a.par0 ^ q;
-    return brick_tile(a, blk - q * a.bpp) * HOP_SITES + lane;
+    const uint32_t lb = (uint32_t)(a.paired ? blk >> 1 : blk - q * a.bpp);
+    p = a.paired ? (int)(blk & 1) : a.par0 ^ q;
+    return brick_tile(a, lb) * HOP_SITES + lane;
 }
 
 // 4-way shape: wave w computes both hops of direction w; waves 1..3 leave
@@ -103,11 +104,12 @@ __global__ __launch_bounds__(256) void hop4_kernel(HopArgs a) {
     const int64_t s = hop_site_index(a, lane, p, blk);
     const Geom &g = a.g;
     const bool active = s < g.vh;
+    // (coordinates of a padding site are never used, and s < 2^31 anyway)
+    const Coord c = cb_coords(g, p, s);
     cplx<T> acc[12];
 #pragma unroll
     for (int k = 0; k < 12; ++k) acc[k] = {0, 0};
     if (active) {
-        const Coord c = cb_coords(g, p, s);
         switch (w) {
             case 0: hop_direction<0, P, LK, DAG, (NTM & 2) != 0>(g, a.in[p], a.U, p, s, c, acc); break;
             case 1: hop_direction<1, P, LK, DAG, (NTM & 2) != 0>(g, a.in[p], a.U, p, s, c, acc); break;
@@ -212,8 +214,9 @@ __global__ __launch_bounds__(512) void hop8_kernel(HopArgs a) {
     const int64_t s = hop_site_index(a, lane, p, blk);
     const Geom &g = a.g;
     const bool active = s < g.vh;
+    // (coordinates of a padding site are never used, and s < 2^31 anyway)
+    const Coord c = cb_coords(g, p, s);
     if (active) {
-        const Coord c = cb_coords(g, p, s);
         cplx<T> x0[3], x1[3];
         switch (w) {
             case 0: hop_single<0, P, LK, DAG, (NTM & 2) != 0>(g, a.in[p], a.U, p, s, c, x0, x1); break;
@@ -323,8 +326,9 @@ static void launch_l(const HopArgs &a, bool dag, bool hasy, bool norm, dim3 grid
 int hop_launch(const HopArgs &a0, int prec, int link, bool dag, int nparity, hipStream_t st) {
     HopArgs a = a0;
     a.bpp = (a.g.vh + HOP_SITES - 1) / HOP_SITES;
-    a.xcd = a.xcd && LQCD_HOP_XCD;
-    a.bz = brick_height(a.g, prec, &a.plane_tiles);
+    int plane_tiles;
+    const int bz = brick_height(a.g, prec, &plane_tiles);
+    a.brick = make_brick(a.g, plane_tiles, bz);
     a.paired = nparity == 2 && LQCD_HOP_PAIRED;
     // row-parallel rebuild where a launch is latency-bound (cache-resident
     // lattices; on large ones the single-wave rebuild is a point faster)
@@ -338,6 +342,7 @@ int hop_launch(const HopArgs &a0, int prec, int link, bool dag, int nparity, hip
     const bool link_nt = LQCD_LINK_NT && !a.paired && spinors + links > INFINITY_CACHE_BYTES;
     a.stream = LQCD_HOP_STREAM >= 0 ? LQCD_HOP_STREAM : (out_nt ? 1 : 0) | (link_nt ? 2 : 0);
     dim3 grid((unsigned)(a.bpp * nparity));
+    a.nblk = grid.x;
     const bool hasy = a.y[0] != nullptr || a.y[1] != nullptr;
     const bool norm = a.partial != nullptr;
     if (prec == LQCD_F64) {
@@ -383,7 +388,6 @@ static int full_hop(const lqcd_geom_t *gg, void *out, const void *in, const void
     a.alpha = alpha;
     a.beta = beta;
     a.par0 = 0;
-    a.xcd = 1;
     // output parity p reads the other parity's half of the input
     a.out[0] = (char *)out;
     a.out[1] = (char *)out + hb;
@@ -420,7 +424,6 @@ static int eo_hop(const lqcd_geom_t *gg, int out_par, void *out, const void *in,
     a.alpha = alpha;
     a.beta = beta;
     a.par0 = out_par;
-    a.xcd = 1;
     a.out[out_par] = (char *)out;
     a.in[out_par] = (const char *)in;
     a.y[out_par] = (const char *)y;

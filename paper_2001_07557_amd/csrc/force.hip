@@ -25,7 +25,7 @@ struct ForceArgs {
     int64_t bpp;  // blocks per parity
     double coeff;
     int mode, accumulate;
-    int plane_tiles, bz;  // brick traversal (bz = 0: plain tile order)
+    Brick brick;  // tile traversal
 };
 
 template <typename T>
@@ -235,7 +235,7 @@ __global__ __launch_bounds__(256) void force_k(ForceArgs a) {
     const int w = threadIdx.x >> 6;
     const int64_t blk = xcd_block(blockIdx.x, gridDim.x);
     const int p = (int)(blk & 1);
-    const int64_t s = brick_order(blk >> 1, a.plane_tiles, a.bz, a.g.L[2], a.g.L[3]) * 64 + lane;
+    const int64_t s = brick_order((uint32_t)(blk >> 1), a.brick) * 64 + lane;
     const bool active = s < a.g.vh;
     if (active) {
         // wave q stages spin rows 2(q & 1) and 2(q & 1) + 1 of X (q < 2) or Y
@@ -296,7 +296,9 @@ extern "C" int lqcd_fermion_force(const lqcd_geom_t *gg, void *F_out, const void
     a.mode = mode;
     a.accumulate = accumulate ? 1 : 0;
     a.bpp = (g.vh + 63) / 64;
-    a.bz = brick_height(g, prec, &a.plane_tiles);
+    int plane_tiles;
+    const int bz = brick_height(g, prec, &plane_tiles);
+    a.brick = make_brick(g, plane_tiles, bz);
     dim3 grid((unsigned)(2 * a.bpp)), block(256);
     hipStream_t st = (hipStream_t)stream;
 #define LQCD_FORCE(P, LK)                                                       \

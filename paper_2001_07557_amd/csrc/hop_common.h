@@ -67,7 +67,22 @@ __device__ __forceinline__ void hop_fence(cplx<T> acc[N]) {
     __builtin_amdgcn_sched_barrier(0);
 }
 
+// Cache-blocked tile order: tiles per (z,t) plane, z-planes per brick, Lt and
+// Lz.  The plain order is the same formula with pt = bz = lz = 1 and lt larger
+// than any tile index, so the traversal needs no branch on the mode.
+struct Brick {
+    FastDiv pt, bz, lt;
+    int lz;
+};
+
 struct HopArgs {
+    // what the site index needs comes first, so that a block reads it with
+    // one wide scalar load
+    int64_t bpp;          // blocks per parity
+    int par0;             // parity of the first bpp blocks
+    int paired;           // both parities: block 2i / 2i + 1 = even / odd tile i
+    uint32_t nblk;        // blocks in the grid
+    Brick brick;          // cache-blocked tile order (identity: plain order)
     Geom g;
     char *out[2];         // output half field for output parity p
     const char *in[2];    // input half field (opposite parity) read by output parity p
@@ -75,14 +90,7 @@ struct HopArgs {
     const char *U;        // gauge field
     double alpha, beta;
     double *partial;      // optional per-block |out|^2
-    int64_t bpp;          // blocks per parity
-    int par0;             // parity of the first bpp blocks
-    int xcd;              // XCD-aware block renumbering
-    // cache-blocked traversal: tiles per (z,t) plane, z-planes per brick
-    // (0 = plain tile order)
-    int plane_tiles, bz;
     int stream;           // non-temporal hints: bit 0 output stores, bit 1 link loads
-    int paired;           // both parities: block 2i / 2i + 1 = even / odd tile i
     int rows;             // 8-way shape: waves 0-3 rebuild one spin row each
 };
 
@@ -91,19 +99,18 @@ struct HopArgs {
 // t-slices of a brick that one output slice touches stay in the XCD's L2,
 // where the plain order would revisit each input slice from memory for the
 // t-neighbours of the slices before and after it.
-__device__ __forceinline__ int64_t brick_order(int64_t b, int plane_tiles, int bz, int lz, int lt) {
-    if (bz == 0) return b;
-    const int64_t pt = b % plane_tiles;
-    int64_t r = b / plane_tiles;
-    const int64_t zi = r % bz;
-    r /= bz;
-    const int64_t t = r % lt;
-    const int64_t zc = r / lt;
-    return ((t * lz + zc * bz + zi) * plane_tiles) + pt;
+__device__ __forceinline__ int64_t brick_order(uint32_t b, const Brick &k) {
+    const uint32_t r1 = fdiv(b, k.pt);   // (z, t) plane in traversal order
+    const uint32_t r2 = fdiv(r1, k.bz);  // (brick, t)
+    const uint32_t zc = fdiv(r2, k.lt);  // brick
+    const uint32_t tile = b - r1 * k.pt.d;
+    const uint32_t zi = r1 - r2 * k.bz.d;
+    const uint32_t t = r2 - zc * k.lt.d;
+    return (int64_t)((t * k.lz + zc * k.bz.d + zi) * k.pt.d + tile);
 }
 
-__device__ __forceinline__ int64_t brick_tile(const HopArgs &a, int64_t b) {
-    return brick_order(b, a.plane_tiles, a.bz, a.g.L[2], a.g.L[3]);
+__device__ __forceinline__ int64_t brick_tile(const HopArgs &a, uint32_t b) {
+    return brick_order(b, a.brick);
 }
 
 // Brick height for the blocked traversal (0 = plain order); needs whole
@@ -129,6 +136,23 @@ inline int brick_height(const Geom &g, int prec, int *plane_tiles) {
         }
     }
     return 0;
+}
+
+// Traversal constants for brick height bz (0: plain order).
+inline Brick make_brick(const Geom &g, int plane_tiles, int bz) {
+    Brick k;
+    if (bz == 0) {
+        k.pt = make_fastdiv(1);
+        k.bz = make_fastdiv(1);
+        k.lt = make_fastdiv((1u << 31) - 1);
+        k.lz = 1;
+    } else {
+        k.pt = make_fastdiv((uint32_t)plane_tiles);
+        k.bz = make_fastdiv((uint32_t)bz);
+        k.lt = make_fastdiv((uint32_t)g.L[3]);
+        k.lz = g.L[2];
+    }
+    return k;
 }
 
 int hop_launch(const HopArgs &a, int prec, int link, bool dag, int nparity, hipStream_t st);

@@ -42,6 +42,9 @@ bool make_geom(const lqcd_geom_t *g, Geom *out) {
     out->sy = out->lxh;
     out->sz = out->sy * g->dims[1];
     out->st = out->sz * g->dims[2];
+    out->dx = make_fastdiv((uint32_t)out->lxh);
+    out->dy = make_fastdiv((uint32_t)g->dims[1]);
+    out->dz = make_fastdiv((uint32_t)g->dims[2]);
     return true;
 }
 

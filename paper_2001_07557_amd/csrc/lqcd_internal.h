@@ -9,6 +9,7 @@
 #include <stddef.h>
 
 #include "../../include/lqcd.h"
+#include "fastdiv.h"
 
 namespace lqcd {
 
@@ -29,6 +30,8 @@ struct Geom {
     int64_t ntiles;
     // checkerboard-index strides of one step in y, z, t
     int64_t sy, sz, st;
+    // divisors lxh, Ly, Lz of a checkerboard index (site -> coordinates)
+    FastDiv dx, dy, dz;
 };
 
 bool make_geom(const lqcd_geom_t *g, Geom *out);
@@ -475,15 +478,18 @@ struct Coord {
     int x, y, z, t;
 };
 
-// Site s (checkerboard index) of parity p -> coordinates.
+// Site s (checkerboard index) of parity p -> coordinates (s < 2^30, so the
+// quotients are 32-bit multiply-and-shift divisions).
 __device__ __forceinline__ Coord cb_coords(const Geom &g, int p, int64_t s) {
     Coord c;
-    const int xh = (int)(s % g.lxh);
-    int64_t r = s / g.lxh;
-    c.y = (int)(r % g.L[1]);
-    r /= g.L[1];
-    c.z = (int)(r % g.L[2]);
-    c.t = (int)(r / g.L[2]);
+    const uint32_t si = (uint32_t)s;
+    const uint32_t r1 = fdiv(si, g.dx);  // (y, z, t) row index
+    const uint32_t r2 = fdiv(r1, g.dy);  // (z, t) plane index
+    const uint32_t t = fdiv(r2, g.dz);
+    const int xh = (int)(si - r1 * g.dx.d);
+    c.y = (int)(r1 - r2 * g.dy.d);
+    c.z = (int)(r2 - t * g.dz.d);
+    c.t = (int)t;
     c.x = 2 * xh + ((p + c.y + c.z + c.t) & 1);
     return c;
 }
@@ -492,11 +498,11 @@ __device__ __forceinline__ Coord cb_coords(const Geom &g, int p, int64_t s) {
 // consecutive workgroups to the 8 XCDs in turn, so block b runs on XCD b % 8;
 // renumbering gives every XCD one contiguous range of tiles (its own L2 then
 // sees the neighbouring sites of its range).  A bijection for any nblocks.
-__device__ __forceinline__ int64_t xcd_block(int64_t b, int64_t nblocks) {
-    constexpr int NX = 8;
-    const int64_t q = nblocks / NX, r = nblocks % NX;
-    const int64_t x = b % NX, k = b / NX;
-    return x * q + (x < r ? x : r) + k;
+__device__ __forceinline__ int64_t xcd_block(uint32_t b, uint32_t nblocks) {
+    constexpr uint32_t NX = 8;
+    const uint32_t q = nblocks / NX, r = nblocks % NX;
+    const uint32_t x = b % NX, k = b / NX;
+    return (int64_t)(x * q + (x < r ? x : r) + k);
 }
 
 // HIP error bookkeeping shared by the entry points.
