@@ -42,6 +42,9 @@ namespace lqcd {
 #define LQCD_HOP_ROWS 1
 #endif
 // both-parity launches pair the even and odd tile of a region (ablation switch)
+#ifndef LQCD_HOP_ARGS_TOUCH
+#define LQCD_HOP_ARGS_TOUCH 1
+#endif
 #ifndef LQCD_HOP_PAIRED
 #define LQCD_HOP_PAIRED 1
 #endif
@@ -81,6 +84,12 @@ __device__ __forceinline__ double hop_epilogue(const HopArgs &a, int p, int64_t 
 // so both are fetched into the same XCD's L2 once.
 __device__ __forceinline__ int64_t hop_site_index(const HopArgs &a, int lane, int &p, int64_t &blk) {
     // selects, not branches: every launch argument is read up front
+#if LQCD_HOP_ARGS_TOUCH
+    // one field from each 64-byte line of the arguments, needed before
+    // anything else: the lines come in with one scalar-cache miss instead of
+    // one after each dependent step
+    asm volatile("" ::"s"(a.bpp), "s"(a.g.vh), "s"(a.g.dz.m), "s"(a.in[0]), "s"(a.stream));
+#endif
     const uint32_t bx = blockIdx.x;
     blk = LQCD_HOP_XCD ? xcd_block(bx, a.nblk) : (int64_t)bx;
     // paired: blocks 2i / 2i + 1 take the even / odd tile i; otherwise the
