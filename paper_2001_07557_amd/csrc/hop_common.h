@@ -50,6 +50,9 @@ constexpr int64_t BRICK_L2_BUDGET = (int64_t)LQCD_BRICK_BUDGET_KB << 10;
 #ifndef LQCD_BRICK_MODE
 #define LQCD_BRICK_MODE 1
 #endif
+#ifndef LQCD_BRICK_MIN_LOG2
+#define LQCD_BRICK_MIN_LOG2 18
+#endif
 // precisions that use the brick order: bit p set for precision p (F64, F32)
 #ifndef LQCD_BRICK_PRECS
 #define LQCD_BRICK_PRECS 3
@@ -118,9 +121,9 @@ __device__ __forceinline__ int64_t brick_tile(const HopArgs &a, uint32_t b) {
 inline int brick_height(const Geom &g, int prec, int *plane_tiles) {
     *plane_tiles = 0;
     if (!LQCD_HOP_BRICK || !((LQCD_BRICK_PRECS >> prec) & 1)) return 0;
-    // small lattices live in the caches anyway, and there the extra index
-    // arithmetic and the loss of plain order cost more (16^4 FP32: 48% -> 40%)
-    if (g.vh < ((int64_t)1 << 18)) return 0;
+    // small lattices live in the caches anyway: only half-lattices of at
+    // least 2^LQCD_BRICK_MIN_LOG2 sites take the blocked order
+    if (g.vh < ((int64_t)1 << LQCD_BRICK_MIN_LOG2)) return 0;
     const int64_t plane = (int64_t)g.lxh * g.L[1];
     if (plane % TILE != 0 || g.vh % TILE != 0) return 0;
     const int64_t pt = plane / TILE;
