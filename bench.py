@@ -50,7 +50,7 @@ KAPPA = 0.124
 
 
 # the sources the hop kernels are compiled from
-HOP_SOURCES = ("dslash.hip", "hop_common.h", "lqcd_internal.h", "reduce.h")
+HOP_SOURCES = ("dslash.hip", "hop_common.h", "lqcd_internal.h", "reduce.h", "fastdiv.h")
 
 
 def log(msg: str) -> None:
