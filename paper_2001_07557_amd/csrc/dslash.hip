@@ -78,6 +78,14 @@ __device__ __forceinline__ double hop_epilogue(const HopArgs &a, int p, int64_t 
     return nrm;
 }
 
+// The five fields read first lie on the five 64-byte lines of the arguments.
+static_assert(sizeof(HopArgs) <= 5 * 64, "launch arguments span more than five lines");
+static_assert(offsetof(HopArgs, bpp) / 64 == 0 &&
+                  (offsetof(HopArgs, g) + offsetof(Geom, vh)) / 64 == 1 &&
+                  (offsetof(HopArgs, g) + offsetof(Geom, dz) + offsetof(FastDiv, m)) / 64 == 2 &&
+                  offsetof(HopArgs, in) / 64 == 3 && offsetof(HopArgs, stream) / 64 == 4,
+              "one touched field per line of the launch arguments");
+
 // Output parity and checkerboard site of this thread (block = one 64-site
 // tile).  A launch over both parities gives consecutive blocks the even and
 // the odd tile of one region: each reads the links and spinors of the other,
