@@ -14,7 +14,9 @@ paper's building blocks under "building_blocks".  "sweep" repeats the hop
 timing on 24^4, 32^4, 48^3x96 and 48^3x12 (one GPU's share of 48^3x96 split
 eight ways in t), and on the benchmark lattice with a
 rotating pool of input copies larger than the Infinity Cache, each also as a
-fraction of a measured copy bandwidth; "grad" times the differentiated
+fraction of a measured copy bandwidth, and times the library's plain copy
+moving the headline launch's algorithmic bytes on a lattice of the same
+extent ("copy_same_bytes"); "grad" times the differentiated
 operator (forward M psi, backward M^dag g and link force) on 24^4.
 
 Timing: one step is captured into a HIP graph (torch.cuda.CUDAGraph around
@@ -218,6 +220,9 @@ def main():
     sweep = None
     if not args.no_sweep and not args.only:
         sweep = run_sweep(P, LI, torch, lattice, dev)
+        if HEADLINE in variants:
+            sweep["copy_same_bytes"] = copy_same_bytes(
+                P, torch, lattice, results[f"{HEADLINE[0]}-{HEADLINE[1]}"]["us_per_launch"])
         torch.cuda.empty_cache()
         log("lattice sweep done")
     grad = None
@@ -345,6 +350,38 @@ def copy_bandwidth(P, torch, dims=(48, 48, 48, 96), reps=10):
     return {"gbs": round(gbs, 1), "frac_hbm": round(gbs / PEAK_HBM, 4),
             "what": f"lqcd_convert FP64 -> FP64 full spinor field, {'x'.join(map(str, dims))}, "
                     "bytes read + written"}
+
+
+def copy_same_bytes(P, torch, lattice, hop_us, apps=100, reps=5):
+    """The headline launch's algorithmic bytes moved by the library's plain
+    copy instead: lqcd_convert between two FP32 full spinor fields whose read
+    plus write bytes equal 576 B x V/2, alternating direction, `apps` copies
+    per HIP graph like the hop's step.  On a cache-resident lattice this is
+    the practical floor of a launch that moves those bytes."""
+    lx, ly, lz, lt = lattice
+    sites = 576 * (lx * ly * lz * lt // 2) // (2 * 96)
+    t = sites // (lx * ly * lz)
+    if t * lx * ly * lz != sites or t % 2:
+        return None
+    lat = P.Lattice((lx, ly, lz, t))
+    a = P.new_spinor(lat, P.F32, P.FULL)
+    a.buf.fill_(1)
+    b = P.new_spinor(lat, P.F32, P.FULL)
+
+    def step():
+        for i in range(apps):
+            if i % 2 == 0:
+                P.convert(b, a)
+            else:
+                P.convert(a, b)
+
+    per = _time_graph(torch, step, reps=reps) / apps
+    del a, b
+    return {"us_per_launch": round(per * 1e6, 3), "gbs": round(2 * 96 * sites / per / 1e9, 1),
+            "hop_us_per_launch": round(hop_us, 3), "hop_over_copy_time": round(hop_us / (per * 1e6), 3),
+            "what": f"lqcd_convert FP32 -> FP32 full spinor field, {lx}x{ly}x{lz}x{t} "
+                    f"({2 * 96 * sites} bytes read + written = the FP32-12 hop launch's "
+                    f"algorithmic bytes), {apps} alternating copies per graph"}
 
 
 def run_sweep(P, LI, torch, lattice, dev, apps=20, steps=5, warmup=2):
