@@ -41,8 +41,8 @@ constexpr int HOP_SITES = 64;  // output sites per block
 // with the XCD renumbering every XCD then owns one z-slab of the lattice and
 // walks it in t order.  Rule 0 takes the largest bz whose three t-slices of
 // input fit LQCD_BRICK_BUDGET_KB.  Measured (fraction of 8 TB/s, 32^4 /
-// 48^3x96, plain order -> rule 1): FP64-18 72.9 -> 77.9 / 61.1 -> 68.8,
-// FP32-12 68.2 -> 78.6 / 63.7 -> 69.9; binary16 gains nothing.
+// 48^3x96, plain order -> rule 1): FP64-18 73.2 -> 78.3 / 60.6 -> 68.6,
+// FP32-12 70.4 -> 83.9 / 65.2 -> 72.2; binary16 gains nothing.
 #ifndef LQCD_BRICK_BUDGET_KB
 #define LQCD_BRICK_BUDGET_KB 3072
 #endif
