@@ -26,13 +26,13 @@ namespace lqcd {
 //    the 256 MB Infinity Cache in front of HBM; when they fit, plain loads
 //    leave them cached for the next application.  A launch over both
 //    parities uses every link twice and always loads them plainly (48^3x96
-//    full-lattice M, FP32-18: 4.3 -> 5.0 TB/s).
+//    full-lattice M, FP32-18: 4.4 -> 5.1 TB/s).
 // Measured (fraction of 8 TB/s, alternating D_eo / D_oe): streaming the
-// output takes FP64-18 from 66.2 to 78.7 at 32^4 and from 64.3 to 68.9 at
-// 48^3x96; cached rather than streamed links take FP32-12 from 71.9 to 80.9
-// at 32^4 (201 MB of links) and FP64-18 from 55.0 to 64.6 at 16^4.  The same
+// output takes FP64-18 from 67.0 to 78.3 at 32^4 and from 64.0 to 68.6 at
+// 48^3x96; cached rather than streamed links take FP32-12 from 75.4 to 83.9
+// at 32^4 (201 MB of links) and FP64-18 from 56.6 to 66.7 at 16^4.  The same
 // hint on the spinor loads would destroy the L2 reuse (LQCD_SPINOR_NT,
-// FP64-18 at 32^4: 50%).  LQCD_OUT_NT / LQCD_LINK_NT = 0 switch a hint off,
+// FP64-18 at 32^4: 51%).  LQCD_OUT_NT / LQCD_LINK_NT = 0 switch a hint off,
 // LQCD_HOP_STREAM = 0..3 forces the mode (ablations).
 #ifndef LQCD_HOP_STREAM
 #define LQCD_HOP_STREAM -1
