@@ -343,9 +343,7 @@ static void launch_l(const HopArgs &a, bool dag, bool hasy, bool norm, dim3 grid
 int hop_launch(const HopArgs &a0, int prec, int link, bool dag, int nparity, hipStream_t st) {
     HopArgs a = a0;
     a.bpp = (a.g.vh + HOP_SITES - 1) / HOP_SITES;
-    int plane_tiles;
-    const int bz = brick_height(a.g, prec, &plane_tiles);
-    a.brick = make_brick(a.g, plane_tiles, bz);
+    a.brick = make_brick(a.g, brick_plan(a.g, prec));
     a.paired = nparity == 2 && LQCD_HOP_PAIRED;
     // row-parallel rebuild where a launch is latency-bound (cache-resident
     // lattices; on large ones the single-wave rebuild is a point faster)

@@ -296,9 +296,7 @@ extern "C" int lqcd_fermion_force(const lqcd_geom_t *gg, void *F_out, const void
     a.mode = mode;
     a.accumulate = accumulate ? 1 : 0;
     a.bpp = (g.vh + 63) / 64;
-    int plane_tiles;
-    const int bz = brick_height(g, prec, &plane_tiles);
-    a.brick = make_brick(g, plane_tiles, bz);
+    a.brick = make_brick(g, brick_plan(g, prec));
     dim3 grid((unsigned)(2 * a.bpp)), block(256);
     hipStream_t st = (hipStream_t)stream;
 #define LQCD_FORCE(P, LK)                                                       \

@@ -39,10 +39,13 @@ constexpr int HOP_SITES = 64;  // output sites per block
 // inside a brick) so the three input t-slices an output slice touches stay in
 // the L2 of the XCD that works on them.  Rule 1 (default) takes bz = Lz/8:
 // with the XCD renumbering every XCD then owns one z-slab of the lattice and
-// walks it in t order.  Rule 0 takes the largest bz whose three t-slices of
-// input fit LQCD_BRICK_BUDGET_KB.  Measured (fraction of 8 TB/s, 32^4 /
-// 48^3x96, plain order -> rule 1): FP64-18 73.2 -> 78.3 / 60.6 -> 68.6,
-// FP32-12 70.4 -> 83.9 / 65.2 -> 72.2; binary16 gains nothing.
+// walks it in t order (Lz/4 where Lz/8 does not fit whole tiles: two XCDs
+// per slab, each with half of its t range).  Rule 0 takes the largest bz
+// whose three t-slices of input fit LQCD_BRICK_BUDGET_KB.  Measured
+// (fraction of 8 TB/s, plain order -> rule 1): 32^4 FP64-18 73.2 -> 78.3,
+// FP32-12 70.4 -> 83.9; 48^3x96 FP64-18 60.6 -> 68.6, FP32-12 65.2 -> 72.2;
+// 24^4 (two-plane groups, four slabs) FP64-18 66.3 -> 77.5, FP32-12 68 -> 73;
+// binary16 gains nothing.
 #ifndef LQCD_BRICK_BUDGET_KB
 #define LQCD_BRICK_BUDGET_KB 3072
 #endif
@@ -51,7 +54,7 @@ constexpr int64_t BRICK_L2_BUDGET = (int64_t)LQCD_BRICK_BUDGET_KB << 10;
 #define LQCD_BRICK_MODE 1
 #endif
 #ifndef LQCD_BRICK_MIN_LOG2
-#define LQCD_BRICK_MIN_LOG2 18
+#define LQCD_BRICK_MIN_LOG2 17
 #endif
 // precisions that use the brick order: bit p set for precision p (F64, F32)
 #ifndef LQCD_BRICK_PRECS
@@ -70,8 +73,8 @@ __device__ __forceinline__ void hop_fence(cplx<T> acc[N]) {
     __builtin_amdgcn_sched_barrier(0);
 }
 
-// Cache-blocked tile order: tiles per (z,t) plane, z-planes per brick, Lt and
-// Lz.  The plain order is the same formula with pt = bz = lz = 1 and lt larger
+// Cache-blocked tile order: tiles per z-group, z-groups per brick, Lt and
+// z-groups in Lz.  The plain order is the same formula with pt = bz = lz = 1 and lt larger
 // than any tile index, so the traversal needs no branch on the mode.
 struct Brick {
     FastDiv pt, bz, lt;
@@ -98,7 +101,7 @@ struct HopArgs {
 };
 
 // Tile visited by logical block b (within one parity).  With bricks of bz
-// z-planes the order is (z-brick, t, z in brick, tile in plane): the three
+// z-groups the order is (z-brick, t, z-group in brick, tile in group): the three
 // t-slices of a brick that one output slice touches stay in the XCD's L2,
 // where the plain order would revisit each input slice from memory for the
 // t-neighbours of the slices before and after it.
@@ -116,44 +119,61 @@ __device__ __forceinline__ int64_t brick_tile(const HopArgs &a, uint32_t b) {
     return brick_order(b, a.brick);
 }
 
-// Brick height for the blocked traversal (0 = plain order); needs whole
-// tiles per (z,t) plane.  See the rules next to LQCD_BRICK_MODE.
-inline int brick_height(const Geom &g, int prec, int *plane_tiles) {
-    *plane_tiles = 0;
-    if (!LQCD_HOP_BRICK || !((LQCD_BRICK_PRECS >> prec) & 1)) return 0;
+// Blocked traversal plan: the tiles of a z-group (the fewest consecutive
+// z-planes whose sites fill whole tiles, usually one plane) form a unit; a
+// brick is bz z-groups and all t.  bz = 0: plain order.
+struct BrickPlan {
+    int pt;  // tiles per z-group
+    int bz;  // z-groups per brick
+    int lz;  // z-groups in Lz
+};
+
+// See the rules next to LQCD_BRICK_MODE.  Rule 1 cuts Lz into 8 bricks (one
+// per XCD), or into 4 when the z-groups do not divide by 8 (two XCDs then
+// share a brick, each taking half of its t range).
+inline BrickPlan brick_plan(const Geom &g, int prec) {
+    BrickPlan k{0, 0, 0};
+    if (!LQCD_HOP_BRICK || !((LQCD_BRICK_PRECS >> prec) & 1)) return k;
     // small lattices live in the caches anyway: only half-lattices of at
     // least 2^LQCD_BRICK_MIN_LOG2 sites take the blocked order
-    if (g.vh < ((int64_t)1 << LQCD_BRICK_MIN_LOG2)) return 0;
+    if (g.vh < ((int64_t)1 << LQCD_BRICK_MIN_LOG2) || g.vh % TILE != 0) return k;
     const int64_t plane = (int64_t)g.lxh * g.L[1];
-    if (plane % TILE != 0 || g.vh % TILE != 0) return 0;
-    const int64_t pt = plane / TILE;
-    if (LQCD_BRICK_MODE == 1 && g.L[2] % 8 == 0 && g.L[2] > 8) {
-        *plane_tiles = (int)pt;
-        return g.L[2] / 8;
-    }
-    const int64_t slice_bytes = pt * spinor_tile_bytes(prec);
-    for (int bz = g.L[2] - 1; bz >= 1; --bz) {
-        if (g.L[2] % bz == 0 && 3 * bz * slice_bytes <= BRICK_L2_BUDGET) {
-            *plane_tiles = (int)pt;
-            return bz;
+    int gz = 1;
+    while (gz <= g.L[2] && (g.L[2] % gz != 0 || (plane * gz) % TILE != 0)) ++gz;
+    if (gz > g.L[2]) return k;
+    const int lz = g.L[2] / gz;
+    const int64_t pt = plane * gz / TILE;
+    if (LQCD_BRICK_MODE == 1) {
+        for (int nb : {8, 4}) {
+            if (lz % nb == 0 && lz / nb >= 2) {
+                k = {(int)pt, lz / nb, lz};
+                return k;
+            }
         }
     }
-    return 0;
+    const int64_t group_bytes = pt * spinor_tile_bytes(prec);
+    for (int bz = lz - 1; bz >= 1; --bz) {
+        if (lz % bz == 0 && 3 * bz * group_bytes <= BRICK_L2_BUDGET) {
+            k = {(int)pt, bz, lz};
+            return k;
+        }
+    }
+    return k;
 }
 
-// Traversal constants for brick height bz (0: plain order).
-inline Brick make_brick(const Geom &g, int plane_tiles, int bz) {
+// Traversal constants of a plan.
+inline Brick make_brick(const Geom &g, const BrickPlan &b) {
     Brick k;
-    if (bz == 0) {
+    if (b.bz == 0) {
         k.pt = make_fastdiv(1);
         k.bz = make_fastdiv(1);
         k.lt = make_fastdiv((1u << 31) - 1);
         k.lz = 1;
     } else {
-        k.pt = make_fastdiv((uint32_t)plane_tiles);
-        k.bz = make_fastdiv((uint32_t)bz);
+        k.pt = make_fastdiv((uint32_t)b.pt);
+        k.bz = make_fastdiv((uint32_t)b.bz);
         k.lt = make_fastdiv((uint32_t)g.L[3]);
-        k.lz = g.L[2];
+        k.lz = b.lz;
     }
     return k;
 }

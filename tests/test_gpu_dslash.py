@@ -265,12 +265,14 @@ def test_hip_graph_replays_match_eager():
 
 
 # Large lattices reach the other traversal orders: (32, 32, 36, 16) has whole
-# tiles per (z, t) plane but Lz is not a multiple of 8, so bricks are sized
-# by the L2 budget; (18, 18, 42, 40) has 162-site planes and a ragged last
-# tile (V/2 = 272160), so tiles are visited in plain order.
+# tiles per (z, t) plane but Lz is not a multiple of 8, so four z-slabs are
+# shared by the eight XCDs; (24, 24, 24, 24) has 288-site planes, so the
+# bricks are made of two-plane groups (nine tiles); (18, 18, 42, 40) has
+# 162-site planes and a ragged last tile (V/2 = 272160), so tiles are visited
+# in plain order.
 @pytest.mark.slow
 @pytest.mark.parametrize("dims", [(32, 32, 32, 32), (48, 48, 48, 96), (32, 32, 36, 16),
-                                  (18, 18, 42, 40)])
+                                  (18, 18, 42, 40), (24, 24, 24, 24)])
 @pytest.mark.parametrize("prec,link", [(P.F64, 18), (P.F64, 12), (P.F32, 12), (P.F32, 18), (P.F16, 12)])
 def test_full_size_sampled(dims, prec, link):
     """Full-size even-odd hops (the launch shapes and traversal orders the
@@ -309,7 +311,8 @@ def test_full_size_sampled(dims, prec, link):
 
 
 @pytest.mark.slow
-@pytest.mark.parametrize("dims", [(32, 32, 32, 32), (32, 32, 36, 16), (18, 18, 42, 40)])
+@pytest.mark.parametrize("dims", [(32, 32, 32, 32), (32, 32, 36, 16), (18, 18, 42, 40),
+                                  (24, 24, 24, 24)])
 @pytest.mark.parametrize("prec,link", [(P.F64, 18), (P.F32, 12), (P.F16, 12)])
 def test_full_lattice_large_sampled(dims, prec, link):
     """Both-parity D_hop (even and odd tiles paired in one launch, links kept
