@@ -341,3 +341,48 @@ def test_full_lattice_large_sampled(dims, prec, link):
         want = dirac.dhop_at(DeviceGather(pr), DeviceGather(Ur), sites, dagger=dag)
         got = res[sites[:, 3], sites[:, 2], sites[:, 1], sites[:, 0]].cpu().numpy()
         assert rel(got, want) < tol
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("dims", [(24, 24, 24, 24), (32, 32, 36, 16), (32, 32, 32, 32)])
+@pytest.mark.parametrize("prec,link", [(P.F64, 18), (P.F64, 12), (P.F32, 18), (P.F32, 12)])
+def test_plane_wave_every_site(dims, prec, link):
+    """Free field (unit links) on a plane wave psi(x) = e^{ip.x} u: D_hop is
+    diagonal, D_hop psi = sum_mu [2 cos p_mu - 2i sin p_mu g_mu] psi (+2i for
+    the adjoint), with the t momentum shifted by pi/L_t for the antiperiodic
+    wrap.  Compared at every output site of the blocked traversals (z-plane
+    groups at 24^4, four slabs at 32x32x36x16, eight at 32^4), so a tile
+    visited twice or never fails, for the even-odd blocks, their adjoints and
+    the both-parity launch."""
+    lat = P.Lattice(dims)
+    lx, ly, lz, lt = dims
+    k = (1, 2, 3, 1)
+    p = (2 * np.pi * k[0] / lx, 2 * np.pi * k[1] / ly, 2 * np.pi * k[2] / lz,
+         (2 * np.pi * k[3] + np.pi) / lt)
+    ct, cz, cy, cx = torch.meshgrid(*[torch.arange(n, device="cuda", dtype=torch.float64)
+                                      for n in (lt, lz, ly, lx)], indexing="ij")
+    phase = torch.exp(1j * (p[0] * cx + p[1] * cy + p[2] * cz + p[3] * ct))
+    rng = np.random.default_rng(21)
+    u = rng.standard_normal((4, 3)) + 1j * rng.standard_normal((4, 3))
+    psi = phase[..., None, None] * dev(u)
+    tdt = torch.complex64 if prec == P.F32 else torch.complex128
+    tol = TOL32 if prec == P.F32 else TOL64
+    eye = torch.eye(3, dtype=tdt, device="cuda")
+    Uf = P.pack_gauge(lat, eye.expand(lt, lz, ly, lx, 4, 3, 3).contiguous(), prec, link)
+    odd = torch.from_numpy(LI.parity_mask(dims)).cuda()
+    for dag in (False, True):
+        sg = 1.0 if dag else -1.0
+        m = sum(2 * np.cos(p[mu]) * np.eye(4) + sg * 2j * np.sin(p[mu]) * dirac.GAMMA[mu]
+                for mu in range(4))
+        want = phase[..., None, None] * dev(m @ u)
+        for out_par, fn in ((P.EVEN, P.meo), (P.ODD, P.moe)):
+            inp = P.pack_spinor(lat, psi.to(tdt), prec, 1 - out_par)
+            out = P.new_spinor(lat, prec, out_par)
+            fn(out, inp, Uf, dagger=dag)
+            sel = odd if out_par == P.ODD else ~odd
+            got = P.unpack_spinor(out)[sel]
+            assert rel(host(got), host(want[sel])) < tol
+        full_in = P.pack_spinor(lat, psi.to(tdt), prec)
+        full_out = P.new_spinor(lat, prec, P.FULL)
+        P.dslash(full_out, full_in, Uf, dagger=dag)
+        assert rel(host(P.unpack_spinor(full_out)), host(want)) < tol
