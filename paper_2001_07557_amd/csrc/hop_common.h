@@ -74,8 +74,9 @@ __device__ __forceinline__ void hop_fence(cplx<T> acc[N]) {
 }
 
 // Cache-blocked tile order: tiles per z-group, z-groups per brick, Lt and
-// z-groups in Lz.  The plain order is the same formula with pt = bz = lz = 1 and lt larger
-// than any tile index, so the traversal needs no branch on the mode.
+// z-groups in Lz.  The plain order is the same formula with pt = bz = lz = 1
+// and lt larger than any tile index, so the traversal needs no branch on the
+// mode.
 struct Brick {
     FastDiv pt, bz, lt;
     int lz;
@@ -101,12 +102,12 @@ struct HopArgs {
 };
 
 // Tile visited by logical block b (within one parity).  With bricks of bz
-// z-groups the order is (z-brick, t, z-group in brick, tile in group): the three
-// t-slices of a brick that one output slice touches stay in the XCD's L2,
+// z-groups the order is (z-brick, t, z-group in brick, tile in group): the
+// three t-slices of a brick that one output slice touches stay in the XCD's L2,
 // where the plain order would revisit each input slice from memory for the
 // t-neighbours of the slices before and after it.
 __device__ __forceinline__ int64_t brick_order(uint32_t b, const Brick &k) {
-    const uint32_t r1 = fdiv(b, k.pt);   // (z, t) plane in traversal order
+    const uint32_t r1 = fdiv(b, k.pt);   // (z-group, t) in traversal order
     const uint32_t r2 = fdiv(r1, k.bz);  // (brick, t)
     const uint32_t zc = fdiv(r2, k.lt);  // brick
     const uint32_t tile = b - r1 * k.pt.d;
