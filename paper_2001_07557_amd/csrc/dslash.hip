@@ -345,9 +345,10 @@ int hop_launch(const HopArgs &a0, int prec, int link, bool dag, int nparity, hip
     a.bpp = (a.g.vh + HOP_SITES - 1) / HOP_SITES;
     a.brick = make_brick(a.g, brick_plan(a.g, prec));
     a.paired = nparity == 2 && LQCD_HOP_PAIRED;
-    // row-parallel rebuild where a launch is latency-bound (cache-resident
-    // lattices; on large ones the single-wave rebuild is a point faster)
-    a.rows = LQCD_HOP_ROWS && a.g.vh < ((int64_t)1 << 18) && a.y[0] == nullptr &&
+    // row-parallel rebuild only where a launch is latency-bound (V/2 < 2^17:
+    // 16^4 and smaller); from 24^4 up the single-wave rebuild is 0.5-2.5
+    // points faster
+    a.rows = LQCD_HOP_ROWS && a.g.vh < ((int64_t)1 << 17) && a.y[0] == nullptr &&
              a.y[1] == nullptr && a.partial == nullptr;
     const int64_t spinors = (int64_t)(nparity * half_spinor_bytes(a.g, prec));
     const int64_t links = (int64_t)gauge_bytes(a.g, prec, link);
