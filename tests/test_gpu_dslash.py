@@ -386,3 +386,46 @@ def test_plane_wave_every_site(dims, prec, link):
         full_out = P.new_spinor(lat, prec, P.FULL)
         P.dslash(full_out, full_in, Uf, dagger=dag)
         assert rel(host(P.unpack_spinor(full_out)), host(want)) < tol
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("dims", [(24, 24, 24, 24), (32, 32, 32, 32)])
+@pytest.mark.parametrize("prec,link", [(P.F64, 18), (P.F64, 12), (P.F32, 12)])
+def test_gamma5_hermiticity_full_size(dims, prec, link):
+    """D_hop^dag = g5 D_hop g5 (g5 = diag(1, 1, -1, -1) in the chiral basis)
+    and <phi, D psi> = <D^dag phi, psi> at full size, every site, with
+    Haar-random links: properties of the operator that hold at any size,
+    checked on the blocked traversals of the even-odd and full-lattice
+    launches (the adjoint kernel against the forward one)."""
+    lat = P.Lattice(dims)
+    Ud, psid = LI.workload_fields_device(12, dims, "cuda")
+    _, phid = LI.workload_fields_device(13, dims, "cuda")
+    tdt = torch.complex64 if prec == P.F32 else torch.complex128
+    tol = TOL32 if prec == P.F32 else TOL64
+    Uf = P.pack_gauge(lat, Ud.to(tdt), prec, link)
+    g5 = torch.tensor([1.0, 1.0, -1.0, -1.0], dtype=tdt, device="cuda")[:, None]
+    psi = psid.to(tdt)
+    # full lattice
+    a = P.pack_spinor(lat, psi, prec)
+    a5 = P.pack_spinor(lat, g5 * psi, prec)
+    d = P.new_spinor(lat, prec, P.FULL)
+    d5 = P.new_spinor(lat, prec, P.FULL)
+    P.dslash(d, a, Uf, dagger=True)
+    P.dslash(d5, a5, Uf)
+    want = g5 * P.unpack_spinor(d5, tdt)
+    assert rel(host(P.unpack_spinor(d, tdt)), host(want)) < tol
+    b = P.pack_spinor(lat, phid.to(tdt), prec)
+    P.dslash(d5, a, Uf)
+    P.dslash(d, b, Uf, dagger=True)
+    lhs, rhs = P.dot(b, d5), P.dot(d, a)
+    assert abs(lhs - rhs) / abs(lhs) < tol
+    # even-odd blocks
+    for out_par, fn in ((P.EVEN, P.meo), (P.ODD, P.moe)):
+        inp = P.pack_spinor(lat, psi, prec, 1 - out_par)
+        inp5 = P.pack_spinor(lat, g5 * psi, prec, 1 - out_par)
+        o = P.new_spinor(lat, prec, out_par)
+        o5 = P.new_spinor(lat, prec, out_par)
+        fn(o, inp, Uf, dagger=True)
+        fn(o5, inp5, Uf)
+        want = g5 * P.unpack_spinor(o5, tdt)
+        assert rel(host(P.unpack_spinor(o, tdt)), host(want)) < tol
