@@ -45,7 +45,7 @@ constexpr int HOP_SITES = 64;  // output sites per block
 // (fraction of 8 TB/s, plain order -> rule 1): 32^4 FP64-18 73.2 -> 78.3,
 // FP32-12 70.4 -> 83.9; 48^3x96 FP64-18 60.6 -> 68.6, FP32-12 65.2 -> 72.2;
 // 24^4 (two-plane groups, four slabs) FP64-18 66.3 -> 77.5, FP32-12 68 -> 73;
-// binary16 gains nothing.
+// binary16 60.7 -> 63.6 at 48^3x96 and 1-2 points at 32^4.
 #ifndef LQCD_BRICK_BUDGET_KB
 #define LQCD_BRICK_BUDGET_KB 3072
 #endif
@@ -56,9 +56,10 @@ constexpr int64_t BRICK_L2_BUDGET = (int64_t)LQCD_BRICK_BUDGET_KB << 10;
 #ifndef LQCD_BRICK_MIN_LOG2
 #define LQCD_BRICK_MIN_LOG2 17
 #endif
-// precisions that use the brick order: bit p set for precision p (F64, F32)
+// precisions that use the brick order: bit p set for precision p (F64, F32,
+// F16)
 #ifndef LQCD_BRICK_PRECS
-#define LQCD_BRICK_PRECS 3
+#define LQCD_BRICK_PRECS 7
 #endif
 
 // Ends one hop: the values carried to the next hop are pinned in registers (an empty asm that
