@@ -16,7 +16,9 @@ eight ways in t), and on the benchmark lattice with a
 rotating pool of input copies larger than the Infinity Cache, each also as a
 fraction of a measured copy bandwidth, and times the library's plain copy
 moving the headline launch's algorithmic bytes on a lattice of the same
-extent ("copy_same_bytes"); "grad" times the differentiated
+extent ("copy_same_bytes"); "split" times the hop of one GPU's share of
+a t decomposition (48^3x12) split into face pack, face exchange, interior
+and boundary launches; "grad" times the differentiated
 operator (forward M psi, backward M^dag g and link force) on 24^4.
 
 Timing: one step is captured into a HIP graph (torch.cuda.CUDAGraph around
@@ -90,9 +92,13 @@ def measured_traffic(lattice, variant):
     return float(m_b.group(1))
 
 
-def cpu_baseline(lattice, budget_s=15.0):
-    """The FP64 oracle's even-odd hop timed on the host on a bounded sample."""
+def cpu_baseline(lattice, budget_s=12.0, cg=None):
+    """The FP64 oracle's even-odd hop timed on the host on a bounded sample,
+    and (with the GPU solve's figures in `cg`) one application of the 32^4
+    normal operator A = Mhat^dag Mhat, the oracle CG's work per iteration,
+    scaled by the GPU's iteration count."""
     import numpy as np
+    import torch
 
     import lattice_inputs as LI
     from oracle import dirac
@@ -110,10 +116,32 @@ def cpu_baseline(lattice, budget_s=15.0):
             break
     wall = time.perf_counter() - w0
     cpu = time.process_time() - c0
-    return {"value": round(FLOP_SITE * 2 * vh * n / wall / 1e9, 4), "unit": "GFlop/s",
-            "cores": max(1, int(round(cpu / wall))), "kind": "oracle",
-            "sample": f"{n} applications of the even-odd operator (D_eo then D_oe) on "
-                      f"{'x'.join(map(str, lattice))}, FP64 numpy oracle, {wall:.1f} s wall"}
+    out = {"value": round(FLOP_SITE * 2 * vh * n / wall / 1e9, 4), "unit": "GFlop/s",
+           "cores": max(1, int(round(cpu / wall))), "host_cores": os.cpu_count(), "kind": "oracle",
+           "sample": f"{n} applications of the even-odd operator (D_eo then D_oe) on "
+                     f"{'x'.join(map(str, lattice))}, FP64 numpy oracle, {wall:.1f} s wall"}
+    if cg is not None:
+        dims = tuple(cg["lattice"])
+        Ud, pd = LI.workload_fields_device(3, dims, "cuda")
+        Uh, ph = Ud.cpu().numpy(), dirac.project(pd.cpu().numpy(), 0)
+        del Ud, pd
+        torch.cuda.empty_cache()
+        w0, c0 = time.perf_counter(), time.process_time()
+        dirac.normal_op(ph, Uh, KAPPA)
+        t_a = time.perf_counter() - w0
+        cpu_a = time.process_time() - c0
+        iters = cg["f64"]["iterations"]
+        out["cg"] = {
+            "seconds_per_iteration": round(t_a, 2), "gpu_iterations": iters,
+            "estimated_seconds_to_1e-10": round(t_a * iters, 1),
+            "gpu_fp64_seconds": cg["f64"]["seconds"], "gpu_f32_inner_seconds": cg["f32-12"]["seconds"],
+            "cores": max(1, int(round(cpu_a / t_a))),
+            "sample": f"one application of A = Mhat^dag Mhat (4 even-odd hops) on "
+                      f"{'x'.join(map(str, dims))} by the FP64 oracle, the operator work of one CG "
+                      f"iteration (vector updates not counted), times the GPU FP64 solve's "
+                      f"iteration count: an estimate of the oracle's time to the 1e-10 residual, "
+                      f"not a measured solve"}
+    return out
 
 
 def main():
@@ -142,6 +170,9 @@ def main():
     ap.add_argument("--no-grad", action="store_true",
                     help="skip the forward / backward timing of the differentiated operator")
     ap.add_argument("--grad-lattice", default="24,24,24,24")
+    ap.add_argument("--no-split", action="store_true",
+                    help="skip the t-decomposition timing (face pack, exchange, interior, boundary)")
+    ap.add_argument("--split-lattice", default="48,48,48,12")
     ap.add_argument("--reductions", action="store_true",
                     help="only time <a,b> and |a|^2 on the lattice and count distinct results")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
@@ -225,6 +256,11 @@ def main():
                 P, torch, lattice, results[f"{HEADLINE[0]}-{HEADLINE[1]}"]["us_per_launch"])
         torch.cuda.empty_cache()
         log("lattice sweep done")
+    split = None
+    if not args.no_split:
+        split = run_split(P, LI, torch, tuple(int(v) for v in args.split_lattice.split(",")), dev)
+        torch.cuda.empty_cache()
+        log("t-split section done")
     grad = None
     if not args.no_grad:
         grad = run_grad(P, LI, torch, tuple(int(v) for v in args.grad_lattice.split(",")), dev)
@@ -258,11 +294,23 @@ def main():
             "bound": "hbm", "achieved": round(gbs, 1), "peak": PEAK_HBM, "unit": "GB/s",
             "frac": round(gbs / PEAK_HBM, 4),
             "traffic": None if traffic is None else round(traffic / t_launch / 1e9, 1),
+            "note": "achieved = algorithmic bytes (8 links + input + output spinor per site) "
+                    "per launch / launch time; the 16^4 half fields stay in the caches between "
+                    "launches, so this is a fraction of algorithmic bytes on a cache-resident, "
+                    "latency-bound launch; the HBM-served fractions of the same kernel follow",
         },
         "variants": results,
     }
     if sweep is not None:
         line["sweep"] = sweep
+        hk = f"{var[0]}-{var[1]}"
+        pool_key = "x".join(map(str, lattice)) + "_pool"
+        for key, name in ((pool_key, "frac_hbm_served_pool"), ("32x32x32x32", "frac_32x32x32x32"),
+                          ("48x48x48x96", "frac_48x48x48x96")):
+            if key in sweep and hk in sweep[key]:
+                line["roofline"][name] = sweep[key][hk]["frac_hbm"]
+    if split is not None:
+        line["split"] = split
     if grad is not None:
         line["grad"] = grad
     if cg is not None:
@@ -273,7 +321,7 @@ def main():
         line["building_blocks"] = blocks
     if not args.no_cpu:
         log("timing the CPU oracle")
-        line["cpu_baseline"] = cpu_baseline(lattice)
+        line["cpu_baseline"] = cpu_baseline(lattice, cg=cg)
     print(json.dumps(line), flush=True)
 
 
@@ -422,6 +470,47 @@ def run_sweep(P, LI, torch, lattice, dev, apps=20, steps=5, warmup=2):
     return out
 
 
+def run_split(P, LI, torch, dims, dev):
+    """One GPU's share of a t decomposition (48^3x12 = 48^3x96 split eight
+    ways in t): the even-odd hop split into the face pack, the exchange (a
+    device copy of the two faces into receive buffers, standing in for the
+    transfer between GPUs), the interior slices and the boundary slices,
+    each timed alone against the unsplit hop (HIP-graph replays)."""
+    lat = P.Lattice(dims)
+    U, psi = LI.workload_fields_device(1, dims, dev)
+    out = {"lattice": list(dims), "what": "D_eo launches; interior = t-slices 1..Lt-2, boundary = "
+                                          "slices 0 and Lt-1 with the t-hops across the boundary "
+                                          "read from the received faces"}
+    for var in (("f64", 18), ("f32", 12), ("f16", 12)):
+        prec = {"f64": P.F64, "f32": P.F32, "f16": P.F16}[var[0]]
+        tdt = torch.complex64 if prec == P.F32 else torch.complex128
+        Uf = P.pack_gauge(lat, U.to(tdt), prec, var[1])
+        inp = P.pack_spinor(lat, psi.to(tdt), prec, P.ODD)
+        o = P.new_spinor(lat, prec, P.EVEN)
+        send = [P.face_buffer(lat, prec), P.face_buffer(lat, prec)]
+        recv = [P.face_buffer(lat, prec), P.face_buffer(lat, prec)]
+
+        def exchange():
+            recv[0].copy_(send[0])
+            recv[1].copy_(send[1])
+
+        t = {"unsplit": _time_graph(torch, lambda: P.meo(o, inp, Uf)),
+             "face_pack": _time_graph(torch, lambda: P.face_pack(send[0], send[1], inp, Uf, P.EVEN)),
+             "exchange_copy": _time_graph(torch, exchange),
+             "interior": _time_graph(torch, lambda: P.hop_region(o, inp, Uf, 0)),
+             "boundary": _time_graph(torch, lambda: P.hop_region(o, inp, Uf, 1, recv[0], recv[1]))}
+        vh = lat.half_volume
+        row = {k + "_us": round(v * 1e6, 2) for k, v in t.items()}
+        row["face_bytes_each"] = int(send[0].numel())
+        row["unsplit_frac_hbm"] = round(BYTES_SITE[var] * vh / t["unsplit"] / 1e9 / PEAK_HBM, 4)
+        row["interior_plus_boundary_over_unsplit"] = round((t["interior"] + t["boundary"]) / t["unsplit"], 3)
+        out[f"{var[0]}-{var[1]}"] = row
+        del Uf, inp, o, send, recv
+        torch.cuda.empty_cache()
+    del U, psi
+    return out
+
+
 def run_grad(P, LI, torch, dims, dev, kappa=KAPPA):
     """The differentiated operator on one lattice: forward M psi and the two
     backward kernels (M^dag g and the link force) as HIP-graph replays, with
@@ -541,8 +630,10 @@ def _time_graph(torch, fn, reps=20):
 def run_blocks(P, LI, torch, dims):
     """Throughput of the paper's building blocks on one lattice: the lattice
     SU(3) product (Fig. 4a-c workload; 3 links of traffic, 198 flop per
-    link), the boundary-aware shift (2 spinors per site) and split_rotate
-    over 64-element FP64 vectors (2 x 8 B per element)."""
+    link), the boundary-aware shift (2 spinors per site), the hopping term
+    composed of generic kernels against the fused one (1320 flop per site
+    each) and split_rotate over 64-element FP64 vectors (2 x 8 B per
+    element)."""
     lat = P.Lattice(dims)
     Ud, psi = LI.workload_fields_device(8, dims, "cuda")
     Vd, _ = LI.workload_fields_device(9, dims, "cuda")
@@ -570,6 +661,23 @@ def run_blocks(P, LI, torch, dims):
             "us": round(t * 1e6, 2), "gbs": round(2 * sb * lat.volume / t / 1e9, 1),
             "frac_hbm": round(2 * sb * lat.volume / t / 1e9 / PEAK_HBM, 4)}
         del src, dst
+    # the hopping term composed of generic kernels (shift, colour product,
+    # projection: 24 launches over full fields) beside the fused kernel, the
+    # analogue of the paper's generic vs hand-unrolled Wilson kernels
+    for prec, link in ((P.F64, 18), (P.F32, 12)):
+        tdt = torch.complex64 if prec == P.F32 else torch.complex128
+        Uf = P.pack_gauge(lat, Ud.to(tdt), prec, link)
+        src = P.pack_spinor(lat, psi.to(tdt), prec)
+        dst = P.new_spinor(lat, prec, P.FULL)
+        t1, t2 = P.new_spinor(lat, prec, P.FULL), P.new_spinor(lat, prec, P.FULL)
+        t_gen = _time_graph(torch, lambda: P.dslash_generic(dst, src, Uf, t1, t2), reps=5)
+        t_fused = _time_graph(torch, lambda: P.dslash(dst, src, Uf))
+        out[f"dslash_generic_{pname[prec]}-{link}"] = {
+            "us": round(t_gen * 1e6, 1), "gflops": round(FLOP_SITE * lat.volume / t_gen / 1e9, 1),
+            "launches": 24, "fused_us": round(t_fused * 1e6, 1),
+            "fused_gflops": round(FLOP_SITE * lat.volume / t_fused / 1e9, 1),
+            "generic_over_fused_time": round(t_gen / t_fused, 2)}
+        del Uf, src, dst, t1, t2
     x = torch.randn(lat.volume * 12, dtype=torch.float64, device="cuda").reshape(-1, 64)
     y = torch.empty_like(x)
     t = _time_graph(torch, lambda: P.split_rotate(y, x, 4, 3))
@@ -613,11 +721,17 @@ def run_solve_force(P, LI, torch, dims, dev, kappa=0.1245):
     b = P.pack_spinor(lat, psid, P.F64, P.EVEN)
     del Ud, psid
     torch.cuda.empty_cache()
+    # the force output is the caller's (allocated outside the timed stages);
+    # a first call brings the kernels in and leaves the intermediate fields in
+    # torch's allocator cache, so the timed call measures the work
+    F = P.new_gauge(lat, P.F32, 18, zero=False)
+    out_warm = P.solve_and_force(b, U_hi, U_lo, kappa, tol=1e-10, out=F)
+    del out_warm
     torch.cuda.synchronize()
     base = torch.cuda.memory_allocated()
     torch.cuda.reset_peak_memory_stats()
     events = []
-    F, st, x, X, Y = P.solve_and_force(b, U_hi, U_lo, kappa, tol=1e-10, events=events)
+    F, st, x, X, Y = P.solve_and_force(b, U_hi, U_lo, kappa, tol=1e-10, events=events, out=F)
     torch.cuda.synchronize()
     ev = dict(events)
     ms = {k: ev["start"].elapsed_time(ev[k]) for k in ("solve", "recompute", "force")}
@@ -629,7 +743,7 @@ def run_solve_force(P, LI, torch, dims, dev, kappa=0.1245):
         "solve_seconds": round(ms["solve"] / 1e3, 4), "iterations": st.iterations,
         "reliable_updates": st.reliable_updates, "true_residual": st.true_residual,
         "recompute_ms": round(ms["recompute"] - ms["solve"], 3),
-        "force_ms": round(force_ms, 3),
+        "force_ms": round(force_ms, 3), "force_output": "preallocated by the caller",
         "force_gbs": round(force_bytes / (force_ms * 1e-3) / 1e9, 1),
         "total_seconds": round(ms["force"] / 1e3, 4),
         "device_gb": {"fields": round(base / 2 ** 30, 2),

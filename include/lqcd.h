@@ -173,6 +173,33 @@ int lqcd_moe(const lqcd_geom_t *g, void *out_o, const void *in_e, const void *y_
              const void *U, double alpha, double beta, int dagger, int prec, int link,
              void *stream);
 
+/* Decomposition in t, the one-GPU part of the paper's multi-node shift
+ * (Sec. 3.1: arrays are split at the domain boundary and the pieces sent to
+ * the neighbouring node).  For the even-odd hop of output parity out_par the
+ * sites of the t-slices 0 and Lt-1 need input across the t boundary; a
+ * sender packs it as two faces, each one value per site of a t-slice:
+ *   face_fwd[j] = bc[3] rows 0, 1 of (1 + S g_t) in(j on slice 0),
+ *   face_bwd[j] = bc[3] U_t(y)^dag rows 0, 1 of (1 - S g_t) in(y = j on slice Lt-1),
+ * S = -1 (S = +1 with dagger != 0), j the checkerboard index within the
+ * slice, `in` the input half field (parity 1 - out_par), U the gauge field.
+ * The receiver multiplies face_fwd by its own U_t.  Faces are stored in the
+ * arithmetic precision (FP32 for binary16 storage) as tiles of 64 sites of
+ * six complex numbers; lqcd_face_bytes gives the size of one face.  On one
+ * GPU the faces of this lattice's own t wrap stand in for the neighbours'.
+ * lqcd_hop_region computes the hop (as lqcd_meo / lqcd_moe: out = alpha
+ * D in + beta y) on region 0, the interior slices 1 .. Lt-2 (no face
+ * needed; faces may be NULL), or region 1, the slices 0 and Lt-1, whose
+ * hops across the t boundary read face_fwd / face_bwd instead of `in`.
+ * Both regions together give the unsplit launch's result bit for bit.  Every
+ * t-slice must be a whole number of 64-site tiles ((Lx/2) Ly Lz divisible by
+ * 64), else LQCD_EINVAL (and lqcd_face_bytes returns 0). */
+size_t lqcd_face_bytes(const lqcd_geom_t *g, int prec);
+int lqcd_face_pack(const lqcd_geom_t *g, void *face_fwd, void *face_bwd, const void *in,
+                   const void *U, int out_par, int dagger, int prec, int link, void *stream);
+int lqcd_hop_region(const lqcd_geom_t *g, int out_par, int region, void *out, const void *in,
+                    const void *y, const void *U, const void *face_fwd, const void *face_bwd,
+                    double alpha, double beta, int dagger, int prec, int link, void *stream);
+
 /* Schur operator on even sites: out_e = Mhat in_e (dagger = 0) or
    Mhat^dag in_e (dagger != 0), Mhat^dag = 1 - kappa^2 (D_oe)^dag (D_eo)^dag.
    tmp_o: caller's odd half field of the same precision (scratch). */
@@ -235,7 +262,10 @@ size_t lqcd_cg_workspace_bytes(const lqcd_geom_t *g, int inner_prec, int inner_l
  *   inner recurrence is not trusted,
  *   and when the inner residual reaches tol.  The solve stops when
  *   ||b - A x|| / ||b|| <= tol in FP64.  The host reads the inner residual
- *   every 10 iterations.
+ *   every 10 iterations while the tolerance is far and every iteration once
+ *   the decay so far puts it within reach, so `iterations` is the first
+ *   iteration whose inner residual reached tol (when the FP64 check then
+ *   confirms it).
  *   workspace: device memory of lqcd_cg_workspace_bytes() bytes.
  *   stats: host struct filled on return (may be NULL).
  * Synchronises the stream.  Returns LQCD_ENOCONV after maxiter inner
@@ -257,7 +287,12 @@ int lqcd_cg_solve(const lqcd_geom_t *g, void *x_e, const void *b_e,
  *   W_mu(x) = coeff * s+_mu(x) [ X(x+mu) (x) ((1-g_mu) Y(x))^dag
  *                              + ((1+g_mu) Y(x+mu)) (x) X(x)^dag ],
  * (a (x) b^dag)_ij = sum_spin a_{s,i} conj(b_{s,j}), the result written is
- *   mode 1: G = W^dag, the raw complex gradient dS/dRe U + i dS/dIm U;
+ *   mode 1: G = W^dag, the raw complex gradient dS/dRe U + i dS/dIm U of
+ *           the 3x3 links the operator applies;
+ *   mode 2: (link = LINK12 only) the raw gradient with respect to the
+ *           stored rows 0 and 1 of 12-real links, whose row 2 the operator
+ *           rebuilds as conj(row0 x row1): row0 = G_0 + conj(row1 x G_2),
+ *           row1 = G_1 + conj(G_2 x row0), row 2 = 0;
  *   mode 0: F = TA(G U^dag), the su(3) force for U -> exp(eps T) U, where
  *           TA(A) = (A - A^dag)/2 - tr(A - A^dag)/6.
  * X, Y: full spinor fields (prec); U: gauge field (prec, link);
@@ -280,6 +315,31 @@ int lqcd_fermion_force(const lqcd_geom_t *g, void *F_out, const void *X, const v
    site scale). */
 int lqcd_cshift(const lqcd_geom_t *g, void *out, const void *in, int mu, int dir, int prec,
                 void *stream);
+
+/* The two per-site operations the generic operator below is composed of
+ * (the paper's generic Wilson kernel, Sec. 3.3 and Fig. 4d, is built from
+ * stencil shifts, Sec. 3.1; these are its other two steps).  Full spinor
+ * fields, prec F64 or F32, out / acc must not alias in.
+ *   lqcd_colour_mul:   out(x) = U_mu(x) in(x), or U_mu(x)^dag in(x) when
+ *                      adjoint != 0, for each of the four spins.
+ *   lqcd_spin_project: acc(x) = (1 + sign g_mu) in(x), sign = +1 or -1,
+ *                      added to acc when accumulate != 0 (else overwritten). */
+int lqcd_colour_mul(const lqcd_geom_t *g, void *out, const void *in, const void *U, int mu,
+                    int adjoint, int prec, int link, void *stream);
+int lqcd_spin_project(const lqcd_geom_t *g, void *acc, const void *in, int mu, int sign,
+                      int accumulate, int prec, void *stream);
+
+/* out = D_hop in (dagger = 0) or D_hop^dag in, composed only of the library's
+ * generic kernels: for each mu, cshift(in, mu, +1) -> colour_mul(U_mu) ->
+ * spin_project(1 - g_mu) and colour_mul(U_mu^dag) -> cshift(-1) ->
+ * spin_project(1 + g_mu) (projectors exchanged for the adjoint), 24 launches
+ * each streaming full fields: the generic counterpart of the fused
+ * lqcd_dslash, as in the paper's comparison of its generic and hand-unrolled
+ * Wilson kernels (Sec. 3.3, Fig. 4d).  tmp1, tmp2: caller's full spinor
+ * fields of the same precision (scratch); no two of out, in, tmp1, tmp2 may
+ * be the same buffer.  prec F64 or F32. */
+int lqcd_dslash_generic(const lqcd_geom_t *g, void *out, const void *in, const void *U,
+                        void *tmp1, void *tmp2, int dagger, int prec, int link, void *stream);
 
 /* The lane permutation of Sec. 3.1 on nvec consecutive vectors of vl
    elements of elem_bytes (8: one double or FP32 complex, 16: one FP64

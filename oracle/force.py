@@ -55,6 +55,25 @@ def link_gradient(X, Y, U, c0, bc=dirac.DEFAULT_BC) -> np.ndarray:
     return G
 
 
+def rows01_gradient(G, U) -> np.ndarray:
+    """Raw gradient with respect to the stored rows 0 and 1 of 12-real links.
+
+    When the operator uses V = (row0, row1, conj(row0 x row1)) built from the
+    stored rows, and G is the raw gradient with respect to V, the chain rule
+    through d row2 = conj(d row0 x row1 + row0 x d row1) gives
+        grad row0 = G_0 + conj(row1 x G_2),   grad row1 = G_1 + conj(G_2 x row0),
+    and zero for the stored row 2, which the operator never reads.
+
+    The paper does not treat derivatives or link compression; chain rule of
+    the standard 12-real form in the conventions of this module's header.
+    """
+    out = np.zeros_like(G)
+    r0, r1, g2 = U[..., 0, :], U[..., 1, :], G[..., 2, :]
+    out[..., 0, :] = G[..., 0, :] + np.conj(np.cross(r1, g2))
+    out[..., 1, :] = G[..., 1, :] + np.conj(np.cross(g2, r0))
+    return out
+
+
 def traceless_antihermitian(a: np.ndarray) -> np.ndarray:
     """TA(A) = (A - A^dag)/2 - tr(A - A^dag)/6 * 1.
 

@@ -59,6 +59,11 @@ SIGNATURES = {
                          c_int, c_int, c_void_p]),
     "lqcd_moe": (c_int, [G, c_void_p, c_void_p, c_void_p, c_void_p, c_double, c_double, c_int,
                          c_int, c_int, c_void_p]),
+    "lqcd_face_bytes": (c_size_t, [G, c_int]),
+    "lqcd_face_pack": (c_int, [G, c_void_p, c_void_p, c_void_p, c_void_p, c_int, c_int, c_int, c_int,
+                               c_void_p]),
+    "lqcd_hop_region": (c_int, [G, c_int, c_int, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
+                                c_void_p, c_double, c_double, c_int, c_int, c_int, c_void_p]),
     "lqcd_mhat": (c_int, [G, c_void_p, c_void_p, c_void_p, c_void_p, c_double, c_int, c_int,
                           c_int, c_void_p]),
     "lqcd_reduce_workspace_bytes": (c_size_t, [G, c_int]),
@@ -75,6 +80,11 @@ SIGNATURES = {
     "lqcd_fermion_force": (c_int, [G, c_void_p, c_void_p, c_void_p, c_void_p, c_double, c_int,
                                    c_int, c_int, c_int, c_void_p]),
     "lqcd_cshift": (c_int, [G, c_void_p, c_void_p, c_int, c_int, c_int, c_void_p]),
+    "lqcd_colour_mul": (c_int, [G, c_void_p, c_void_p, c_void_p, c_int, c_int, c_int, c_int,
+                                c_void_p]),
+    "lqcd_spin_project": (c_int, [G, c_void_p, c_void_p, c_int, c_int, c_int, c_int, c_void_p]),
+    "lqcd_dslash_generic": (c_int, [G, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_int,
+                                    c_int, c_int, c_void_p]),
     "lqcd_split_rotate": (c_int, [c_void_p, c_void_p, ctypes.c_int64, c_int, c_int, c_int, c_int,
                                   c_void_p]),
     "lqcd_su3_mul": (c_int, [G, c_void_p, c_void_p, c_void_p, c_int, c_int, c_int, c_int,

@@ -5,9 +5,12 @@ backward pass runs two library kernels:
 
 * dL/dpsi = M^dag g (the adjoint hopping kernel),
 * dL/dU from the fermion-force kernel with X = psi, Y = g, c0 = -kappa: the raw
-  complex gradient G = dL/dRe U + i dL/dIm U (``link_grad="raw"``, what torch
-  optimisers and gradcheck expect) or the su(3)-projected force
-  F = TA(G U^dag) for U -> exp(eps T) U (``link_grad="su3"``).
+  complex gradient G = dL/dRe U + i dL/dIm U of the function computed
+  (``link_grad="raw"``, what torch optimisers and gradcheck expect; with
+  12-real links the operator reads only rows 0 and 1 of U and rebuilds row 2,
+  so the kernel carries G through that rebuild and row 2 gets zero) or the
+  su(3)-projected force F = TA(G U^dag) for U -> exp(eps T) U
+  (``link_grad="su3"``).
 
 Only psi and U are saved for backward; phi is not kept.
 """
@@ -26,7 +29,7 @@ class WilsonMatrix(torch.autograd.Function):
             raise ValueError("link_grad is 'raw' or 'su3'")
         Uf = L.pack_gauge(lattice, U.contiguous(), prec, link)
         pf = L.pack_spinor(lattice, psi.contiguous(), prec, L.FULL)
-        of = L.new_spinor(lattice, prec, L.FULL, psi.device)
+        of = L.new_spinor(lattice, prec, L.FULL, psi.device, zero=False)
         L.wilson(of, pf, Uf, kappa)
         ctx.save_for_backward(psi, U)
         ctx.cfg = (kappa, lattice, prec, link, link_grad)
@@ -40,12 +43,16 @@ class WilsonMatrix(torch.autograd.Function):
         gf = L.pack_spinor(lattice, g.contiguous().to(psi.dtype), prec, L.FULL)
         gpsi = gU = None
         if ctx.needs_input_grad[0]:
-            of = L.new_spinor(lattice, prec, L.FULL, psi.device)
+            of = L.new_spinor(lattice, prec, L.FULL, psi.device, zero=False)
             L.wilson(of, gf, Uf, kappa, dagger=True)
             gpsi = L.unpack_spinor(of, dtype=psi.dtype)
         if ctx.needs_input_grad[1]:
             pf = L.pack_spinor(lattice, psi.contiguous(), prec, L.FULL)
-            F = L.fermion_force(pf, gf, Uf, -kappa, mode=1 if link_grad == "raw" else 0)
+            if link_grad == "su3":
+                mode = 0
+            else:
+                mode = 2 if link == L.LINK12 else 1
+            F = L.fermion_force(pf, gf, Uf, -kappa, mode=mode)
             gU = L.unpack_gauge(F, dtype=U.dtype)
         return gpsi, gU, None, None, None, None, None
 
@@ -97,16 +104,16 @@ class NormalSolve(torch.autograd.Function):
             gb = L.unpack_spinor(lam).to(g.dtype)
         if ctx.needs_input_grad[1]:
             x = L.pack_spinor(lat, xe, L.F64, L.EVEN)
-            tmp = L.new_spinor(lat, L.F64, L.ODD, dev)
+            tmp = L.new_spinor(lat, L.F64, L.ODD, dev, zero=False)
 
             def x_field(v):  # (v, D_oe v)
-                f = L.new_spinor(lat, L.F64, L.FULL, dev)
-                L.axpby(1.0, v, 0.0, f.half(L.EVEN))
+                f = L.new_spinor(lat, L.F64, L.FULL, dev, zero=False)
+                L.convert(f.half(L.EVEN), v)
                 L.moe(f.half(L.ODD), v, U_hi)
                 return f
 
             def y_field(v):  # (Mhat v, (D_eo)^dag Mhat v)
-                f = L.new_spinor(lat, L.F64, L.FULL, dev)
+                f = L.new_spinor(lat, L.F64, L.FULL, dev, zero=False)
                 L.mhat(f.half(L.EVEN), v, tmp, U_hi, kappa)
                 L.moe(f.half(L.ODD), f.half(L.EVEN), U_hi, dagger=True)
                 return f

@@ -3,10 +3,12 @@
 // sloppy gauge field (FP64, FP32 or binary16 storage with FP32 arithmetic),
 // global sums are FP64 and fixed-order, and the true residual b - A x is
 // recomputed in FP64 every `reliable_every` iterations, whenever a
-// reduced-precision inner residual has fallen tenfold since the last update,
-// and whenever the inner residual reaches the tolerance.  CG scalars live in device memory, so an
-// iteration is a stream of kernels with no host round trip; the host reads
-// the residual only every few iterations.
+// reduced-precision inner residual has fallen by 1/delta since the last
+// update (delta below), and whenever the inner residual reaches the
+// tolerance.  CG scalars live in device memory, so an iteration is a stream
+// of kernels with no host round trip; the host reads the residual every few
+// iterations, and every iteration once the decay so far says the tolerance
+// is near, so the solve stops at the first iteration that reaches it.
 //
 // Per iteration: 4 hop kernels (the second also produces |Mhat p|^2 = <p, A p>
 // block partials), one fused x += a p, r -= a Ap, |r|^2 kernel, p = r + b p,
@@ -213,6 +215,21 @@ static CGWork cg_layout(const Geom &g, int prec, char *base) {
     return w;
 }
 
+// Iterations until the next host read of the inner residual: CHECK_EVERY
+// while the tolerance is far, fewer as the geometric decay between the last
+// two reads (rr0 at k0, rr1 at k1) says it is near, and one once it is
+// within about one iteration, so the solve stops at the first iteration
+// whose residual reaches it instead of up to CHECK_EVERY - 1 later.
+static int next_read_after(double rr0, int k0, double rr1, int k1, double target) {
+    if (!(rr1 > target) || k1 <= k0 || !(rr0 > 0.0) || !(rr1 < rr0)) {
+        return rr1 > target && rr1 < 100.0 * target ? 1 : CHECK_EVERY;
+    }
+    const double per_iter = std::log(rr1 / rr0) / (double)(k1 - k0);  // < 0
+    const double left = std::log(target / rr1) / per_iter;             // > 0
+    const double n = std::floor(0.7 * left);
+    return n < 1.0 ? 1 : n > CHECK_EVERY ? CHECK_EVERY : (int)n;
+}
+
 struct Solver {
     Geom g;
     hipStream_t st;
@@ -340,6 +357,10 @@ struct Solver {
         double rr_ref = rr;  // true residual at the last reliable update
         const double delta = P == LQCD_F64 ? 0.0 : P == LQCD_F32 ? DELTA_F32 : DELTA_F16;
         const double drift = delta * delta;
+        // residual at the last host read, and the iteration of the next one
+        int k_seen = 0;
+        double rr_seen = rr;
+        int next_read = CHECK_EVERY;
         while (true) {
             rc = apply_a(P, link, U, w.p, w.ap, w.te, w.to, w.partial);
             if (rc) return rc;
@@ -350,7 +371,7 @@ struct Solver {
             if (rc) return rc;
             ++k;
             bool reliable = reliable_every > 0 && k % reliable_every == 0;
-            if (reliable || k % CHECK_EVERY == 0 || k >= maxiter) {
+            if (reliable || k >= next_read || k >= maxiter) {
                 rc = read(&rr_it, S_RR);
                 if (rc) return rc;
                 if (!std::isfinite(rr_it)) {
@@ -358,6 +379,9 @@ struct Solver {
                     return LQCD_ENAN;
                 }
                 if (rr_it <= target || rr_it < drift * rr_ref) reliable = true;
+                next_read = k + next_read_after(rr_seen, k_seen, rr_it, k, target);
+                rr_seen = rr_it;
+                k_seen = k;
             }
             if (reliable || k >= maxiter) {
                 cg_fold_k<P><<<grid(), CG_BLOCK, 0, st>>>(x64, w.xs, g.vh);
@@ -375,6 +399,9 @@ struct Solver {
                 launch_convert(g, 1, w.rs, P, w.r64, LQCD_F64, st);
                 rc = norm_into<OP_RESET>(w.rs, P);
                 if (rc) return rc;
+                rr_seen = rr;
+                k_seen = k;
+                next_read = k + next_read_after(rr_ref, k, rr, k, target);
             }
             cg_direction_k<P><<<grid(), CG_BLOCK, 0, st>>>(w.p, w.rs, w.sc, g.vh);
         }

@@ -48,6 +48,11 @@ namespace lqcd {
 #ifndef LQCD_HOP_PAIRED
 #define LQCD_HOP_PAIRED 1
 #endif
+// extra LDS bytes per 4-way block (ablation switch): limits the blocks in
+// flight per CU, and with them the window of tiles an XCD's L2 must hold
+#ifndef LQCD_HOP_EXTRA_LDS
+#define LQCD_HOP_EXTRA_LDS 0
+#endif
 constexpr int64_t INFINITY_CACHE_BYTES = (int64_t)256 << 20;
 
 // Epilogue shared by both kernel shapes: out = alpha acc + beta y, optional |out|^2.
@@ -110,7 +115,7 @@ __device__ __forceinline__ int64_t hop_site_index(const HopArgs &a, int lane, in
 
 // 4-way shape: wave w computes both hops of direction w; waves 1..3 leave
 // their partial spinors in LDS and wave 0 adds them up.
-template <int P, int LK, bool DAG, bool HASY, bool NORM, int NTM>
+template <int P, int LK, bool DAG, bool HASY, bool NORM, int NTM, bool HALO>
 __global__ __launch_bounds__(256) void hop4_kernel(HopArgs a) {
     using T = typename real_of<P>::type;
     __shared__ cplx<T> part[3][12][64];
@@ -127,11 +132,12 @@ __global__ __launch_bounds__(256) void hop4_kernel(HopArgs a) {
 #pragma unroll
     for (int k = 0; k < 12; ++k) acc[k] = {0, 0};
     if (active) {
+        constexpr bool LNT = (NTM & 2) != 0;
         switch (w) {
-            case 0: hop_direction<0, P, LK, DAG, (NTM & 2) != 0>(g, a.in[p], a.U, p, s, c, acc); break;
-            case 1: hop_direction<1, P, LK, DAG, (NTM & 2) != 0>(g, a.in[p], a.U, p, s, c, acc); break;
-            case 2: hop_direction<2, P, LK, DAG, (NTM & 2) != 0>(g, a.in[p], a.U, p, s, c, acc); break;
-            default: hop_direction<3, P, LK, DAG, (NTM & 2) != 0>(g, a.in[p], a.U, p, s, c, acc); break;
+            case 0: hop_direction<0, P, LK, DAG, LNT>(g, a.in[p], a.U, p, s, c, acc); break;
+            case 1: hop_direction<1, P, LK, DAG, LNT>(g, a.in[p], a.U, p, s, c, acc); break;
+            case 2: hop_direction<2, P, LK, DAG, LNT>(g, a.in[p], a.U, p, s, c, acc); break;
+            default: hop_direction<3, P, LK, DAG, LNT, HALO>(g, a.in[p], a.U, p, s, c, acc, a.face); break;
         }
     }
     if (w > 0) {
@@ -154,6 +160,43 @@ __global__ __launch_bounds__(256) void hop4_kernel(HopArgs a) {
             const double t = wave_sum(nrm[0]);
             if (lane == 0) a.partial[blk] = t;
         }
+    }
+}
+
+// 1-way shape (ablation builds, LQCD_HOP_SHAPE_* = 1): one wave per block,
+// every thread computes all eight hops of its site in registers, no LDS.
+// The four directions are added in the 4-way shape's order.
+template <int P, int LK, bool DAG, bool HASY, bool NORM, int NTM, bool HALO>
+__global__ __launch_bounds__(64) void hop1_kernel(HopArgs a) {
+    using T = typename real_of<P>::type;
+    const int lane = threadIdx.x & 63;
+    int p;
+    int64_t blk;
+    const int64_t s = hop_site_index(a, lane, p, blk);
+    const Geom &g = a.g;
+    const bool active = s < g.vh;
+    const Coord c = cb_coords(g, p, s);
+    cplx<T> acc[12], d[12];
+#pragma unroll
+    for (int k = 0; k < 12; ++k) acc[k] = {0, 0};
+    double nrm[1] = {0.0};
+    if (active) {
+        constexpr bool LNT = (NTM & 2) != 0;
+        hop_direction<0, P, LK, DAG, LNT>(g, a.in[p], a.U, p, s, c, acc);
+        hop_direction<1, P, LK, DAG, LNT>(g, a.in[p], a.U, p, s, c, d);
+#pragma unroll
+        for (int k = 0; k < 12; ++k) acc[k] = acc[k] + d[k];
+        hop_direction<2, P, LK, DAG, LNT>(g, a.in[p], a.U, p, s, c, d);
+#pragma unroll
+        for (int k = 0; k < 12; ++k) acc[k] = acc[k] + d[k];
+        hop_direction<3, P, LK, DAG, LNT, HALO>(g, a.in[p], a.U, p, s, c, d, a.face);
+#pragma unroll
+        for (int k = 0; k < 12; ++k) acc[k] = acc[k] + d[k];
+        nrm[0] = hop_epilogue<P, HASY, NORM, (NTM & 1) != 0>(a, p, s, acc);
+    }
+    if constexpr (NORM) {
+        const double t = wave_sum(nrm[0]);
+        if (lane == 0) a.partial[blk] = t;
     }
 }
 
@@ -220,7 +263,7 @@ __device__ __forceinline__ void rebuild_row(const HopArgs &a, int p, int64_t s,
 // 8-way shape: wave w computes hop w (direction w/2, forward for even w) and
 // stages the two colour vectors of its multiplied half-spinor in LDS; wave 0
 // rebuilds the four spin rows from the eight staged half-spinors.
-template <int P, int LK, bool DAG, bool HASY, bool NORM, int NTM, bool ROWS>
+template <int P, int LK, bool DAG, bool HASY, bool NORM, int NTM, bool ROWS, bool HALO>
 __global__ __launch_bounds__(512) void hop8_kernel(HopArgs a) {
     using T = typename real_of<P>::type;
     __shared__ cplx<T> chi[8][6][64];
@@ -235,15 +278,16 @@ __global__ __launch_bounds__(512) void hop8_kernel(HopArgs a) {
     const Coord c = cb_coords(g, p, s);
     if (active) {
         cplx<T> x0[3], x1[3];
+        constexpr bool LNT = (NTM & 2) != 0;
         switch (w) {
-            case 0: hop_single<0, P, LK, DAG, (NTM & 2) != 0>(g, a.in[p], a.U, p, s, c, x0, x1); break;
-            case 1: hop_single<1, P, LK, DAG, (NTM & 2) != 0>(g, a.in[p], a.U, p, s, c, x0, x1); break;
-            case 2: hop_single<2, P, LK, DAG, (NTM & 2) != 0>(g, a.in[p], a.U, p, s, c, x0, x1); break;
-            case 3: hop_single<3, P, LK, DAG, (NTM & 2) != 0>(g, a.in[p], a.U, p, s, c, x0, x1); break;
-            case 4: hop_single<4, P, LK, DAG, (NTM & 2) != 0>(g, a.in[p], a.U, p, s, c, x0, x1); break;
-            case 5: hop_single<5, P, LK, DAG, (NTM & 2) != 0>(g, a.in[p], a.U, p, s, c, x0, x1); break;
-            case 6: hop_single<6, P, LK, DAG, (NTM & 2) != 0>(g, a.in[p], a.U, p, s, c, x0, x1); break;
-            default: hop_single<7, P, LK, DAG, (NTM & 2) != 0>(g, a.in[p], a.U, p, s, c, x0, x1); break;
+            case 0: hop_single<0, P, LK, DAG, LNT>(g, a.in[p], a.U, p, s, c, x0, x1); break;
+            case 1: hop_single<1, P, LK, DAG, LNT>(g, a.in[p], a.U, p, s, c, x0, x1); break;
+            case 2: hop_single<2, P, LK, DAG, LNT>(g, a.in[p], a.U, p, s, c, x0, x1); break;
+            case 3: hop_single<3, P, LK, DAG, LNT>(g, a.in[p], a.U, p, s, c, x0, x1); break;
+            case 4: hop_single<4, P, LK, DAG, LNT>(g, a.in[p], a.U, p, s, c, x0, x1); break;
+            case 5: hop_single<5, P, LK, DAG, LNT>(g, a.in[p], a.U, p, s, c, x0, x1); break;
+            case 6: hop_single<6, P, LK, DAG, LNT, HALO>(g, a.in[p], a.U, p, s, c, x0, x1, a.face); break;
+            default: hop_single<7, P, LK, DAG, LNT, HALO>(g, a.in[p], a.U, p, s, c, x0, x1, a.face); break;
         }
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
@@ -295,19 +339,34 @@ constexpr int hop_shape(int prec) {
                                                                      : LQCD_HOP_SHAPE_F16;
 }
 
-template <int P, int LK, bool DAG, bool HASY, bool NORM, int NTM>
-static void launch_nt(const HopArgs &a, dim3 grid, hipStream_t st) {
-    if constexpr (hop_shape(P) == 8) {
+template <int P, int LK, bool DAG, bool HASY, bool NORM, int NTM, bool HALO>
+static void launch_halo(const HopArgs &a, dim3 grid, hipStream_t st) {
+    if constexpr (hop_shape(P) == 1) {
+        hop1_kernel<P, LK, DAG, HASY, NORM, NTM, HALO><<<grid, 64, 0, st>>>(a);
+    } else if constexpr (hop_shape(P) == 8) {
         if constexpr (P == LQCD_F32 && !HASY && !NORM) {
             if (a.rows) {
-                hop8_kernel<P, LK, DAG, HASY, NORM, NTM, true><<<grid, 512, 0, st>>>(a);
+                hop8_kernel<P, LK, DAG, HASY, NORM, NTM, true, HALO><<<grid, 512, 0, st>>>(a);
                 return;
             }
         }
-        hop8_kernel<P, LK, DAG, HASY, NORM, NTM, false><<<grid, 512, 0, st>>>(a);
+        hop8_kernel<P, LK, DAG, HASY, NORM, NTM, false, HALO><<<grid, 512, 0, st>>>(a);
     } else {
-        hop4_kernel<P, LK, DAG, HASY, NORM, NTM><<<grid, 256, 0, st>>>(a);
+        hop4_kernel<P, LK, DAG, HASY, NORM, NTM, HALO><<<grid, 256, LQCD_HOP_EXTRA_LDS, st>>>(a);
     }
+}
+
+// Boundary-slice launches (faces given) have no norm partial; the face
+// variants exist only for the other combinations.
+template <int P, int LK, bool DAG, bool HASY, bool NORM, int NTM>
+static void launch_nt(const HopArgs &a, dim3 grid, hipStream_t st) {
+    if constexpr (!NORM) {
+        if (a.face[0] != nullptr) {
+            launch_halo<P, LK, DAG, HASY, NORM, NTM, true>(a, grid, st);
+            return;
+        }
+    }
+    launch_halo<P, LK, DAG, HASY, NORM, NTM, false>(a, grid, st);
 }
 
 // The cache hints are template arguments: a run-time choice between two
@@ -340,10 +399,24 @@ static void launch_l(const HopArgs &a, bool dag, bool hasy, bool norm, dim3 grid
     else launch_p<P, LK, false>(a, hasy, norm, grid, st);
 }
 
-int hop_launch(const HopArgs &a0, int prec, int link, bool dag, int nparity, hipStream_t st) {
+int hop_launch(const HopArgs &a0, int prec, int link, bool dag, int nparity, hipStream_t st,
+               int region) {
     HopArgs a = a0;
-    a.bpp = (a.g.vh + HOP_SITES - 1) / HOP_SITES;
-    a.brick = make_brick(a.g, brick_plan(a.g, prec));
+    if (region < 0) {
+        a.bpp = (a.g.vh + HOP_SITES - 1) / HOP_SITES;
+        a.brick = make_brick(a.g, brick_plan(a.g, prec));
+        a.face[0] = a.face[1] = nullptr;
+    } else {
+        // interior slices 1 .. Lt-2, or boundary slices 0 and Lt-1
+        const int lt = a.g.L[3];
+        const int nt = region == 0 ? lt - 2 : 2;
+        if (nt <= 0) return LQCD_OK;
+        a.bpp = (int64_t)nt * (a.g.st / TILE);
+        a.brick = make_region_brick(a.g, brick_plan(a.g, prec), region == 0 ? 1 : 0,
+                                    region == 0 ? 1 : lt - 1, nt);
+        if (region == 0) a.face[0] = a.face[1] = nullptr;
+        nparity = 1;
+    }
     a.paired = nparity == 2 && LQCD_HOP_PAIRED;
     // row-parallel rebuild only where a launch is latency-bound (V/2 < 2^17:
     // 16^4 and smaller); from 24^4 up the single-wave rebuild is 0.5-2.5
@@ -457,6 +530,34 @@ extern "C" int lqcd_moe(const lqcd_geom_t *g, void *out_o, const void *in_e, con
                         const void *U, double alpha, double beta, int dagger, int prec, int link,
                         void *stream) {
     return eo_hop(g, LQCD_ODD, out_o, in_e, y_o, U, alpha, beta, dagger, prec, link, stream);
+}
+
+extern "C" int lqcd_hop_region(const lqcd_geom_t *gg, int out_par, int region, void *out,
+                               const void *in, const void *y, const void *U,
+                               const void *face_fwd, const void *face_bwd, double alpha,
+                               double beta, int dagger, int prec, int link, void *stream) {
+    Geom g;
+    int rc = validate_hop(gg, &g, out, in, U, prec, link);
+    if (rc) return rc;
+    if (out_par != LQCD_EVEN && out_par != LQCD_ODD) return LQCD_EINVAL;
+    if (region != 0 && region != 1) return LQCD_EINVAL;
+    if (g.st % TILE != 0) return LQCD_EINVAL;  // t-slices must be whole tiles
+    if (y && ((uintptr_t)y & 15)) return LQCD_EINVAL;
+    if (region == 1 && (!face_fwd || !face_bwd || (((uintptr_t)face_fwd | (uintptr_t)face_bwd) & 15)))
+        return LQCD_EINVAL;
+    HopArgs a{};
+    a.g = g;
+    a.U = (const char *)U;
+    a.alpha = alpha;
+    a.beta = beta;
+    a.par0 = out_par;
+    a.out[out_par] = (char *)out;
+    a.in[out_par] = (const char *)in;
+    a.y[out_par] = (const char *)y;
+    a.partial = nullptr;
+    a.face[0] = (const char *)face_fwd;
+    a.face[1] = (const char *)face_bwd;
+    return hop_launch(a, prec, link, dagger != 0, 1, (hipStream_t)stream, region);
 }
 
 extern "C" int lqcd_mhat(const lqcd_geom_t *g, void *out_e, const void *in_e, void *tmp_o,

@@ -4,8 +4,10 @@
 // Because (1 -+ g_mu)/2 is a rank-two hermitian projector, each spin sum
 // reduces to two colour outer products of projected half-spinors:
 //   sum_s a_s (x) ((1-g) b)_s^dag = sum_{u=0,1} h_u[(1-g) a] (x) h_u[(1-g) b]^dag.
-// Output: mode 1 the raw gradient G = W^dag, mode 0 the su(3) force
-// F = TA(G U^dag) = -TA(U W), TA(A) = (A - A^dag)/2 - tr(A - A^dag)/6.
+// Output: mode 1 the raw gradient G = W^dag, mode 2 (12-real links) that
+// gradient carried through the row-2 rebuild onto the stored rows 0 and 1,
+// mode 0 the su(3) force F = TA(G U^dag) = -TA(U W),
+// TA(A) = (A - A^dag)/2 - tr(A - A^dag)/6.
 
 #include "lqcd_internal.h"
 #include "hop_common.h"
@@ -55,8 +57,9 @@ __device__ __forceinline__ int64_t force_neighbour(const Geom &g, int64_t s, con
     }
 }
 
-// Scale W by the coefficient and boundary sign, form G = W^dag (mode 1) or
-// F = -TA(U W) (mode 0), optionally add the old output, store.
+// Scale W by the coefficient and boundary sign, form G = W^dag (mode 1; mode
+// 2 carries it onto the stored rows of a 12-real link) or F = -TA(U W)
+// (mode 0), optionally add the old output, store.
 template <int MU, int P, int LK>
 __device__ __forceinline__ void force_store(const ForceArgs &a, int p, int64_t s, bool flip,
                                             cplx<typename real_of<P>::type> w[9]) {
@@ -67,12 +70,31 @@ __device__ __forceinline__ void force_store(const ForceArgs &a, int p, int64_t s
     for (int k = 0; k < 9; ++k) w[k] = scale(cs, w[k]);
 
     cplx<T> out[9];
-    if (a.mode == 1) {
+    if (a.mode != 0) {
         // G = W^dag
 #pragma unroll
         for (int i = 0; i < 3; ++i)
 #pragma unroll
             for (int j = 0; j < 3; ++j) out[3 * i + j] = conj(w[3 * j + i]);
+        if (a.mode == 2) {
+            // gradient with respect to the stored rows 0, 1 of a 12-real link:
+            // row 2 = conj(row0 x row1) chains G_2 into them,
+            //   row0 += conj(row1 x G_2),  row1 += conj(G_2 x row0),  row2 = 0
+            cplx<T> u[9];
+            load_link<P, LK>(a.U, g.ntiles, p, s, MU, u);
+            const cplx<T> d0[3] = {conj_cross(u[4], out[8], u[5], out[7]),
+                                   conj_cross(u[5], out[6], u[3], out[8]),
+                                   conj_cross(u[3], out[7], u[4], out[6])};
+            const cplx<T> d1[3] = {conj_cross(out[7], u[2], out[8], u[1]),
+                                   conj_cross(out[8], u[0], out[6], u[2]),
+                                   conj_cross(out[6], u[1], out[7], u[0])};
+#pragma unroll
+            for (int j = 0; j < 3; ++j) {
+                out[j] = out[j] + d0[j];
+                out[3 + j] = out[3 + j] + d1[j];
+                out[6 + j] = {0, 0};
+            }
+        }
     } else {
         cplx<T> u[9];
         load_link<P, LK>(a.U, g.ntiles, p, s, MU, u);
@@ -281,7 +303,7 @@ extern "C" int lqcd_fermion_force(const lqcd_geom_t *gg, void *F_out, const void
     if (!make_geom(gg, &g)) return LQCD_EINVAL;
     if (prec != LQCD_F64 && prec != LQCD_F32) return LQCD_EINVAL;
     if (!valid_link(prec, link)) return LQCD_EINVAL;
-    if (mode != 0 && mode != 1) return LQCD_EINVAL;
+    if (mode != 0 && mode != 1 && !(mode == 2 && link == 12)) return LQCD_EINVAL;
     if (!F_out || !X || !Y || !U) return LQCD_EINVAL;
     if (((uintptr_t)F_out | (uintptr_t)X | (uintptr_t)Y | (uintptr_t)U) & 15) return LQCD_EINVAL;
     if (F_out == X || F_out == Y || F_out == U) return LQCD_EINVAL;

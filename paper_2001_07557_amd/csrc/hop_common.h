@@ -11,10 +11,12 @@ namespace lqcd {
 //   8-way: 512 threads, wave w computes hop w alone and stages the two colour
 //          vectors of its multiplied half-spinor in LDS, where wave 0 rebuilds
 //          the four spin rows (FP32 storage).
-// Measured on gfx950 against one thread per site: the split shapes win at
-// every size (more waves in flight, shorter dependent load chains), 8-way is
-// ahead for FP32 and 4-way for FP64 and binary16 (fewer LDS bytes per hop).
-// The LQCD_HOP_SHAPE_* macros exist for ablation builds.
+// Measured on gfx950 against one thread per site doing all eight hops in
+// registers without LDS (shape 1, kept for ablation builds): the split
+// shapes win at every size (more waves in flight, shorter dependent load
+// chains), 8-way is ahead for FP32 and 4-way for FP64 and binary16 (fewer
+// LDS bytes per hop).  The LQCD_HOP_SHAPE_* macros (1, 4 or 8) select the
+// shape per precision in ablation builds.
 #ifndef LQCD_HOP_SHAPE_F64
 #define LQCD_HOP_SHAPE_F64 4
 #endif
@@ -81,6 +83,10 @@ __device__ __forceinline__ void hop_fence(cplx<T> acc[N]) {
 struct Brick {
     FastDiv pt, bz, lt;
     int lz;
+    // t-slices visited: t0, t0 + tstep, ... (lt of them); a whole-lattice
+    // launch has t0 = 0, tstep = 1, a region launch (interior or boundary
+    // slices of a t decomposition) other values
+    uint32_t t0, tstep;
 };
 
 struct HopArgs {
@@ -100,6 +106,10 @@ struct HopArgs {
     double *partial;      // optional per-block |out|^2
     int stream;           // non-temporal hints: bit 0 output stores, bit 1 link loads
     int rows;             // 8-way shape: waves 0-3 rebuild one spin row each
+    // boundary-slice launches: the t-hops that cross the t boundary read
+    // face[0] (projected half-spinors of the forward neighbours) and face[1]
+    // (U^dag times the projected backward neighbours) instead of `in`
+    const char *face[2];
 };
 
 // Tile visited by logical block b (within one parity).  With bricks of bz
@@ -113,7 +123,7 @@ __device__ __forceinline__ int64_t brick_order(uint32_t b, const Brick &k) {
     const uint32_t zc = fdiv(r2, k.lt);  // brick
     const uint32_t tile = b - r1 * k.pt.d;
     const uint32_t zi = r1 - r2 * k.bz.d;
-    const uint32_t t = r2 - zc * k.lt.d;
+    const uint32_t t = k.t0 + (r2 - zc * k.lt.d) * k.tstep;
     return (int64_t)((t * k.lz + zc * k.bz.d + zi) * k.pt.d + tile);
 }
 
@@ -177,10 +187,33 @@ inline Brick make_brick(const Geom &g, const BrickPlan &b) {
         k.lt = make_fastdiv((uint32_t)g.L[3]);
         k.lz = b.lz;
     }
+    k.t0 = 0;
+    k.tstep = 1;
     return k;
 }
 
-int hop_launch(const HopArgs &a, int prec, int link, bool dag, int nparity, hipStream_t st);
+// Traversal of the t-slices t0, t0 + tstep, ... (nt of them) only, each a
+// whole number of tiles: the lattice's blocked order restricted to those
+// slices, or slice by slice in tile order where the lattice has no blocked
+// order.
+inline Brick make_region_brick(const Geom &g, const BrickPlan &b, int t0, int tstep, int nt) {
+    Brick k = make_brick(g, b);
+    if (b.bz == 0) {
+        k.pt = make_fastdiv((uint32_t)(g.st / TILE));
+        k.bz = make_fastdiv(1);
+        k.lz = 1;
+    }
+    k.lt = make_fastdiv((uint32_t)nt);
+    k.t0 = (uint32_t)t0;
+    k.tstep = (uint32_t)tstep;
+    return k;
+}
+
+// region: -1 the whole half lattice; 0 the interior t-slices 1 .. Lt-2;
+// 1 the boundary slices 0 and Lt-1, whose t-hops across the boundary read
+// a.face (slices must be whole tiles for regions 0 and 1)
+int hop_launch(const HopArgs &a, int prec, int link, bool dag, int nparity, hipStream_t st,
+               int region = -1);
 int64_t hop_partials(const Geom &g, int nparity);
 
 // Spin projection (1 + S g_mu): with the unit constants of the chiral basis,
@@ -226,22 +259,27 @@ __device__ __forceinline__ cplx<T> add_unit(cplx<E> a, cplx<E> b, T one) {
     else return {fmad(bi, one, ar), fmad(br, -one, ai)};
 }
 
-// Project with (1 + S g_mu), apply the boundary sign and multiply by U (or
-// U^dag): the two colour vectors chi0, chi1 of one hop.
-template <int MU, int S, bool UDAG, typename T, typename E>
-__device__ __forceinline__ void hop_chi(const cplx<E> psi[12], const cplx<T> u[9], T sign,
-                                        cplx<T> x0[3], cplx<T> x1[3]) {
+// Project with (1 + S g_mu) and apply the boundary sign: rows 0 and 1 of the
+// half-spinor of one hop.
+template <int MU, int S, typename T, typename E>
+__device__ __forceinline__ void hop_half(const cplx<E> psi[12], T sign, cplx<T> h0[3],
+                                         cplx<T> h1[3]) {
     using PR = Proj<MU>;
     constexpr int k0 = S > 0 ? PR::c0 : neg_code(PR::c0);
     constexpr int k1 = S > 0 ? PR::c1 : neg_code(PR::c1);
     T one = 1;
     if constexpr (sizeof(E) == 2) asm volatile("" : "+v"(one));
-    cplx<T> h0[3], h1[3];
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
         h0[c] = scale(sign, add_unit<k0, T>(psi[c], psi[PR::a0 * 3 + c], one));
         h1[c] = scale(sign, add_unit<k1, T>(psi[3 + c], psi[PR::a1 * 3 + c], one));
     }
+}
+
+// chi = U h (or U^dag h) for the two colour vectors of a half-spinor.
+template <bool UDAG, typename T>
+__device__ __forceinline__ void half_mul(const cplx<T> u[9], const cplx<T> h0[3],
+                                         const cplx<T> h1[3], cplx<T> x0[3], cplx<T> x1[3]) {
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
         if constexpr (UDAG) {
@@ -252,6 +290,61 @@ __device__ __forceinline__ void hop_chi(const cplx<E> psi[12], const cplx<T> u[9
             x1[a] = cdot3(u[3 * a], h1[0], u[3 * a + 1], h1[1], u[3 * a + 2], h1[2]);
         }
     }
+}
+
+// Project with (1 + S g_mu), apply the boundary sign and multiply by U (or
+// U^dag): the two colour vectors chi0, chi1 of one hop.
+template <int MU, int S, bool UDAG, typename T, typename E>
+__device__ __forceinline__ void hop_chi(const cplx<E> psi[12], const cplx<T> u[9], T sign,
+                                        cplx<T> x0[3], cplx<T> x1[3]) {
+    cplx<T> h0[3], h1[3];
+    hop_half<MU, S>(psi, sign, h0, h1);
+    half_mul<UDAG>(u, h0, h1, x0, x1);
+}
+
+// Face buffers of a t decomposition: per site of one t-slice (index j within
+// the slice, tiles of 64 sites) two colour vectors (six complex numbers) in
+// the arithmetic precision, as 16-byte words: FP64 six words of one complex,
+// FP32 three words of two.
+template <typename T>
+__device__ __forceinline__ void load_face(const char *__restrict__ f, int64_t j, cplx<T> v[6]) {
+    const int lane = (int)(j & (TILE - 1));
+    if constexpr (sizeof(T) == 8) {
+        const v2d *w = reinterpret_cast<const v2d *>(f + (j >> TILE_SHIFT) * (6 * TILE * WORD)) + lane;
+#pragma unroll
+        for (int k = 0; k < 6; ++k) {
+            const v2d d = w[k * TILE];
+            v[k] = {d.x, d.y};
+        }
+    } else {
+        const v4f *w = reinterpret_cast<const v4f *>(f + (j >> TILE_SHIFT) * (3 * TILE * WORD)) + lane;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            const v4f d = w[k * TILE];
+            v[2 * k] = {d.x, d.y};
+            v[2 * k + 1] = {d.z, d.w};
+        }
+    }
+}
+
+template <typename T>
+__device__ __forceinline__ void store_face(char *__restrict__ f, int64_t j, const cplx<T> v[6]) {
+    const int lane = (int)(j & (TILE - 1));
+    if constexpr (sizeof(T) == 8) {
+        v2d *w = reinterpret_cast<v2d *>(f + (j >> TILE_SHIFT) * (6 * TILE * WORD)) + lane;
+#pragma unroll
+        for (int k = 0; k < 6; ++k) w[k * TILE] = v2d{v[k].re, v[k].im};
+    } else {
+        v4f *w = reinterpret_cast<v4f *>(f + (j >> TILE_SHIFT) * (3 * TILE * WORD)) + lane;
+#pragma unroll
+        for (int k = 0; k < 3; ++k)
+            w[k * TILE] = v4f{v[2 * k].re, v[2 * k].im, v[2 * k + 1].re, v[2 * k + 1].im};
+    }
+}
+
+// Bytes of one face buffer (one t-slice of one parity) for storage precision prec.
+inline size_t face_bytes(const Geom &g, int prec) {
+    return (size_t)g.st * 6 * (prec == LQCD_F64 ? 16 : 8);
 }
 
 // Add one hop's chi0, chi1 into the four spin rows of acc.
@@ -297,15 +390,36 @@ __device__ __forceinline__ int64_t hop_neighbour(const Geom &g, int64_t s, const
 }
 
 // chi of the single hop H (0..7: direction H/2, forward for even H) of site s.
-template <int H, int P, int LK, bool DAG, bool LNT>
+// HALO: the t-hops that cross the t boundary take their half-spinor (forward)
+// or its product with U^dag (backward) from the face buffers.
+template <int H, int P, int LK, bool DAG, bool LNT, bool HALO = false>
 __device__ __forceinline__ void hop_single(const Geom &g, const char *__restrict__ in,
                                            const char *__restrict__ U, int p, int64_t s,
                                            const Coord &c, cplx<typename real_of<P>::type> x0[3],
-                                           cplx<typename real_of<P>::type> x1[3]) {
+                                           cplx<typename real_of<P>::type> x1[3],
+                                           const char *const *face = nullptr) {
     using T = typename real_of<P>::type;
     constexpr int MU = H >> 1;
     constexpr bool FWD = (H & 1) == 0;
     constexpr int S = FWD ? (DAG ? 1 : -1) : (DAG ? -1 : 1);
+    if constexpr (HALO && MU == 3) {
+        if (FWD ? c.t == g.L[3] - 1 : c.t == 0) {
+            cplx<T> h[6];
+            load_face<T>(face[FWD ? 0 : 1], FWD ? s - (int64_t)(g.L[3] - 1) * g.st : s, h);
+            if constexpr (FWD) {
+                cplx<T> u[9];
+                load_link<P, LK, LNT>(U, g.ntiles, p, s, MU, u);
+                half_mul<false>(u, h, h + 3, x0, x1);
+            } else {
+#pragma unroll
+                for (int a = 0; a < 3; ++a) {
+                    x0[a] = h[a];
+                    x1[a] = h[3 + a];
+                }
+            }
+            return;
+        }
+    }
     bool flip;
     const int64_t nb = hop_neighbour<MU, FWD>(g, s, c, flip);
     cplx<typename hop_elem<P>::type> psi[12];
@@ -329,21 +443,32 @@ struct HopSign {
 //   rows 0,1 = chi_f + chi_b,   rows a0,a1 = (unit of the forward hop) (chi_f - chi_b).
 // Only the forward hop's two colour vectors (6 complex numbers) stay live
 // while the backward hop loads, instead of a full 12-row accumulator.
-template <int MU, int P, int LK, bool DAG, bool LNT>
+template <int MU, int P, int LK, bool DAG, bool LNT, bool HALO = false>
 __device__ __forceinline__ void hop_direction(const Geom &g, const char *__restrict__ in,
                                               const char *__restrict__ U, int p, int64_t s,
-                                              const Coord &c, cplx<typename real_of<P>::type> acc[12]) {
+                                              const Coord &c, cplx<typename real_of<P>::type> acc[12],
+                                              const char *const *face = nullptr) {
     using T = typename real_of<P>::type;
     using PR = Proj<MU>;
     constexpr int SF = DAG ? 1 : -1;
     constexpr int SB = -SF;
     constexpr int r0 = SF > 0 ? conj_code(PR::c0) : neg_code(conj_code(PR::c0));
     constexpr int r1 = SF > 0 ? conj_code(PR::c1) : neg_code(conj_code(PR::c1));
+    // HALO (boundary-slice launches): a t-hop that crosses the t boundary
+    // reads the face buffers instead of `in`
+    constexpr bool TFACE = HALO && MU == 3;
+    const bool face_f = TFACE && c.t == g.L[3] - 1;
+    const bool face_b = TFACE && c.t == 0;
     bool flip_f, flip_b;
     const int64_t fwd = hop_neighbour<MU, true>(g, s, c, flip_f);
     const int64_t bwd = hop_neighbour<MU, false>(g, s, c, flip_b);
     cplx<T> f[6];
-    {
+    if (face_f) {
+        cplx<T> h[6], u[9];
+        load_face<T>(face[0], s - (int64_t)(g.L[3] - 1) * g.st, h);
+        load_link<P, LK, LNT>(U, g.ntiles, p, s, MU, u);
+        half_mul<false>(u, h, h + 3, f, f + 3);
+    } else {
         T sgn = flip_f ? T(-1) : T(1);
         cplx<typename hop_elem<P>::type> psi[12];
         cplx<T> u[9];
@@ -353,12 +478,17 @@ __device__ __forceinline__ void hop_direction(const Geom &g, const char *__restr
     }
     hop_fence<T, 6>(f);
     {
-        T sgn = flip_b ? T(-1) : T(1);
-        cplx<typename hop_elem<P>::type> psi[12];
-        cplx<T> u[9], b[6];
-        load_spinor_hop<P>(in, bwd, psi, sgn);
-        load_link<P, LK, LNT>(U, g.ntiles, p ^ 1, bwd, MU, u);
-        hop_chi<MU, SB, true>(psi, u, sgn, b, b + 3);
+        cplx<T> b[6];
+        if (face_b) {
+            load_face<T>(face[1], s, b);
+        } else {
+            T sgn = flip_b ? T(-1) : T(1);
+            cplx<typename hop_elem<P>::type> psi[12];
+            cplx<T> u[9];
+            load_spinor_hop<P>(in, bwd, psi, sgn);
+            load_link<P, LK, LNT>(U, g.ntiles, p ^ 1, bwd, MU, u);
+            hop_chi<MU, SB, true>(psi, u, sgn, b, b + 3);
+        }
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
             acc[a] = f[a] + b[a];

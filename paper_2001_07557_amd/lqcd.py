@@ -140,15 +140,21 @@ class GaugeField:
         return self.buf.data_ptr()
 
 
-def new_spinor(lat: Lattice, prec: int, subset: int, device=None) -> SpinorField:
+def new_spinor(lat: Lattice, prec: int, subset: int, device=None, zero: bool = True) -> SpinorField:
+    """A spinor field in the internal layout; zero=False leaves it
+    uninitialised (for outputs that a kernel overwrites entirely)."""
     buf = _device_bytes(lat.spinor_bytes(prec, subset), device)
-    buf.zero_()
+    if zero:
+        buf.zero_()
     return SpinorField(lat, prec, subset, buf)
 
 
-def new_gauge(lat: Lattice, prec: int, link: int, device=None) -> GaugeField:
+def new_gauge(lat: Lattice, prec: int, link: int, device=None, zero: bool = True) -> GaugeField:
+    """A gauge (or force) field in the internal layout; zero=False leaves it
+    uninitialised."""
     buf = _device_bytes(lat.gauge_bytes(prec, link), device)
-    buf.zero_()
+    if zero:
+        buf.zero_()
     return GaugeField(lat, prec, link, buf)
 
 
@@ -165,7 +171,8 @@ def pack_spinor(lat: Lattice, psi: torch.Tensor, prec: int, subset: int = FULL,
     """Canonical complex[Lt][Lz][Ly][Lx][4][3] -> internal (only `subset` sites read)."""
     if tuple(psi.shape) != lat.spinor_shape():
         raise RuntimeError(f"spinor shape {tuple(psi.shape)} != {lat.spinor_shape()}")
-    f = out if out is not None else new_spinor(lat, prec, subset, psi.device)
+    # every site of the field (a half field holds one parity) is written
+    f = out if out is not None else new_spinor(lat, prec, subset, psi.device, zero=False)
     _check(_lib.load().lqcd_pack_spinor(lat.ref(), f.ptr, _ptr(psi), _canon_prec(psi), prec,
                                         subset, _stream()), "pack_spinor")
     return f
@@ -176,7 +183,9 @@ def unpack_spinor(f: SpinorField, dtype=torch.complex128, out: Optional[torch.Te
     left as they were in `out`)."""
     lat = f.lattice
     if out is None:
-        out = torch.zeros(lat.spinor_shape(), dtype=dtype, device=f.buf.device)
+        # a half field leaves the other parity's sites untouched: zero them
+        alloc = torch.empty if f.subset == FULL else torch.zeros
+        out = alloc(lat.spinor_shape(), dtype=dtype, device=f.buf.device)
     _check(_lib.load().lqcd_unpack_spinor(lat.ref(), _ptr(out), f.ptr, _canon_prec(out), f.prec,
                                           f.subset, _stream()), "unpack_spinor")
     return out
@@ -186,7 +195,7 @@ def pack_gauge(lat: Lattice, U: torch.Tensor, prec: int, link: int) -> GaugeFiel
     """Canonical complex[Lt][Lz][Ly][Lx][4][3][3] -> internal links."""
     if tuple(U.shape) != lat.links_shape():
         raise RuntimeError(f"links shape {tuple(U.shape)} != {lat.links_shape()}")
-    f = new_gauge(lat, prec, link, U.device)
+    f = new_gauge(lat, prec, link, U.device, zero=False)
     _check(_lib.load().lqcd_pack_gauge(lat.ref(), f.ptr, _ptr(U), _canon_prec(U), prec, link,
                                        _stream()), "pack_gauge")
     return f
@@ -249,6 +258,43 @@ def moe(out: SpinorField, inp: SpinorField, U: GaugeField, alpha: float = 1.0, b
         raise RuntimeError("moe maps an even half field to an odd one")
     _check(_lib.load().lqcd_moe(out.lattice.ref(), out.ptr, inp.ptr, y.ptr if y is not None else None,
                                 U.ptr, alpha, beta, int(dagger), U.prec, U.link, _stream()), "moe")
+    return out
+
+
+def face_buffer(lat: Lattice, prec: int, device=None) -> torch.Tensor:
+    """Device buffer for one t-face (lqcd_face_bytes bytes)."""
+    n = _lib.load().lqcd_face_bytes(lat.ref(), prec)
+    if n == 0:
+        raise LQCDError(EINVAL, "face_bytes (t-slices must be whole 64-site tiles)")
+    return _device_bytes(n, device)
+
+
+def face_pack(face_fwd: torch.Tensor, face_bwd: torch.Tensor, inp: SpinorField, U: GaugeField,
+              out_parity: int, dagger: bool = False):
+    """Pack the two t-faces the hop of output parity `out_parity` needs from
+    across the t boundary (inp: the input half field, parity 1 - out_parity)."""
+    _same(inp, U)
+    if inp.subset != 1 - out_parity:
+        raise RuntimeError("face_pack reads the half field of the other parity")
+    _check(_lib.load().lqcd_face_pack(inp.lattice.ref(), _ptr(face_fwd), _ptr(face_bwd), inp.ptr,
+                                      U.ptr, out_parity, int(dagger), U.prec, U.link, _stream()),
+           "face_pack")
+
+
+def hop_region(out: SpinorField, inp: SpinorField, U: GaugeField, region: int,
+               face_fwd: Optional[torch.Tensor] = None, face_bwd: Optional[torch.Tensor] = None,
+               alpha: float = 1.0, beta: float = 0.0, y: Optional[SpinorField] = None,
+               dagger: bool = False):
+    """The even-odd hop into `out` (parity out.subset) on region 0 (t-slices
+    1 .. Lt-2) or region 1 (slices 0 and Lt-1, t boundary read from the faces)."""
+    _same(out, inp, y, U)
+    if out.subset not in (EVEN, ODD) or inp.subset != 1 - out.subset or (
+            y is not None and y.subset != out.subset):
+        raise RuntimeError("hop_region maps a half field to the other parity")
+    _check(_lib.load().lqcd_hop_region(out.lattice.ref(), out.subset, region, out.ptr, inp.ptr,
+                                       y.ptr if y is not None else None, U.ptr, _ptr(face_fwd),
+                                       _ptr(face_bwd), alpha, beta, int(dagger), U.prec, U.link,
+                                       _stream()), "hop_region")
     return out
 
 
@@ -344,11 +390,12 @@ def cg_solve(x: SpinorField, b: SpinorField, U_hi: GaugeField, U_lo: GaugeField,
 def fermion_force(X: SpinorField, Y: SpinorField, U: GaugeField, coeff: float, mode: int = 0,
                   out: Optional[GaugeField] = None, accumulate: bool = False) -> GaugeField:
     """Link derivative of coeff * Re(Y^dag D_hop X): mode 0 su(3) force
-    F = TA(G U^dag), mode 1 raw gradient G (both LINK18 fields)."""
+    F = TA(G U^dag), mode 1 raw gradient G, mode 2 (12-real U only) G carried
+    onto the stored rows 0 and 1 (all LINK18 fields)."""
     _same(X, Y, U)
     lat = X.lattice
     if out is None:
-        out = new_gauge(lat, U.prec, LINK18, X.buf.device)
+        out = new_gauge(lat, U.prec, LINK18, X.buf.device, zero=accumulate)
     _check(_lib.load().lqcd_fermion_force(lat.ref(), out.ptr, X.ptr, Y.ptr, U.ptr, coeff, mode,
                                           int(accumulate), U.prec, U.link, _stream()),
            "fermion_force")
@@ -357,7 +404,8 @@ def fermion_force(X: SpinorField, Y: SpinorField, U: GaugeField, coeff: float, m
 
 def solve_and_force(phi_e: SpinorField, U_hi: GaugeField, U_lo: GaugeField, kappa: float,
                     tol: float = 1e-10, maxiter: int = 20000, reliable_every: int = 100,
-                    U_force: Optional[GaugeField] = None, events: Optional[list] = None):
+                    U_force: Optional[GaugeField] = None, events: Optional[list] = None,
+                    out: Optional[GaugeField] = None):
     """Pseudofermion solve plus force for S = phi_e^dag (Mhat^dag Mhat)^-1 phi_e.
 
     1. X_e = (Mhat^dag Mhat)^-1 phi_e by mixed-precision CG (FP64 result);
@@ -365,7 +413,8 @@ def solve_and_force(phi_e: SpinorField, U_hi: GaugeField, U_lo: GaugeField, kapp
        kernels in the force precision (nothing from the solve is kept but X_e);
     3. F = TA(G U^dag) with G the link derivative of 2 kappa^2 Re(Y^dag dD_hop X).
     U_force (default U_lo; an FP32 field when U_lo is binary16) sets the
-    precision of steps 2-3.  Returns (F, cg stats, X_e, X, Y).  With
+    precision of steps 2-3.  Returns (F, cg stats, X_e, X, Y); `out` (a
+    LINK18 field of the force precision) receives F if given.  With
     `events` a list, (stage name, torch.cuda.Event) pairs are appended at the
     start and after each stage, on the current stream.
     """
@@ -386,20 +435,17 @@ def solve_and_force(phi_e: SpinorField, U_hi: GaugeField, U_lo: GaugeField, kapp
                      reliable_every=reliable_every)
     mark("solve")
     fp = Uf.prec
-    X = new_spinor(lat, fp, FULL, x.buf.device)
-    Y = new_spinor(lat, fp, FULL, x.buf.device)
+    X = new_spinor(lat, fp, FULL, x.buf.device, zero=False)
+    Y = new_spinor(lat, fp, FULL, x.buf.device, zero=False)
     Xe, Xo, Ye, Yo = X.half(EVEN), X.half(ODD), Y.half(EVEN), Y.half(ODD)
-    if fp == F64:
-        axpby(1.0, x, 0.0, Xe)
-    else:
-        convert(Xe, x)
+    convert(Xe, x)  # a copy (FP64) or a rounding to the force precision
     moe(Xo, Xe, Uf)
-    tmp = new_spinor(lat, fp, ODD, x.buf.device)
+    tmp = new_spinor(lat, fp, ODD, x.buf.device, zero=False)
     mhat(Ye, Xe, tmp, Uf, kappa)
     moe(Yo, Ye, Uf, dagger=True)
     del tmp
     mark("recompute")
-    F = fermion_force(X, Y, Uf, 2.0 * kappa * kappa, mode=0)
+    F = fermion_force(X, Y, Uf, 2.0 * kappa * kappa, mode=0, out=out)
     mark("force")
     return F, stats, x, X, Y
 
@@ -415,6 +461,42 @@ def cshift(out: SpinorField, inp: SpinorField, mu: int, direction: int) -> Spino
         raise RuntimeError("cshift works on full fields")
     _check(_lib.load().lqcd_cshift(out.lattice.ref(), out.ptr, inp.ptr, mu, direction, out.prec,
                                    _stream()), "cshift")
+    return out
+
+
+def colour_mul(out: SpinorField, inp: SpinorField, U: GaugeField, mu: int,
+               adjoint: bool = False) -> SpinorField:
+    """out(x) = U_mu(x) inp(x) (U_mu(x)^dag with adjoint) on full fields."""
+    _same(out, inp, U)
+    if out.subset != FULL or inp.subset != FULL:
+        raise RuntimeError("colour_mul works on full fields")
+    _check(_lib.load().lqcd_colour_mul(out.lattice.ref(), out.ptr, inp.ptr, U.ptr, mu,
+                                       int(adjoint), U.prec, U.link, _stream()), "colour_mul")
+    return out
+
+
+def spin_project(acc: SpinorField, inp: SpinorField, mu: int, sign: int,
+                 accumulate: bool = True) -> SpinorField:
+    """acc(x) (+)= (1 + sign g_mu) inp(x) on full fields."""
+    _same(acc, inp)
+    if acc.subset != FULL or inp.subset != FULL:
+        raise RuntimeError("spin_project works on full fields")
+    _check(_lib.load().lqcd_spin_project(acc.lattice.ref(), acc.ptr, inp.ptr, mu, sign,
+                                         int(accumulate), acc.prec, _stream()), "spin_project")
+    return acc
+
+
+def dslash_generic(out: SpinorField, inp: SpinorField, U: GaugeField, tmp1: SpinorField,
+                   tmp2: SpinorField, dagger: bool = False) -> SpinorField:
+    """out = D_hop inp (D_hop^dag with dagger) composed of the generic kernels
+    (shift, colour product, projector); tmp1, tmp2 are full scratch fields."""
+    _same(out, inp, U, tmp1, tmp2)
+    for f in (out, inp, tmp1, tmp2):
+        if f.subset != FULL:
+            raise RuntimeError("dslash_generic works on full fields")
+    _check(_lib.load().lqcd_dslash_generic(out.lattice.ref(), out.ptr, inp.ptr, U.ptr, tmp1.ptr,
+                                           tmp2.ptr, int(dagger), U.prec, U.link, _stream()),
+           "dslash_generic")
     return out
 
 

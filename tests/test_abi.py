@@ -108,6 +108,9 @@ def test_invalid_arguments_rejected(lib):
     assert st.status == -5
     # reductions: NULL result pointer
     assert lib.lqcd_norm2(ctypes.byref(g), 0, a, 0, ws, None, None) == -1
+    # force: mode 2 (rows 0, 1 of 12-real links) needs 12-real links
+    assert lib.lqcd_fermion_force(ctypes.byref(g), a, b, ctypes.c_void_p(12288), u, 1.0, 2, 0, 0,
+                                  18, None) == -1
 
 
 def test_product_path_has_no_cpu_fallback():
@@ -138,6 +141,27 @@ def test_volume_limit_and_empty_vectors(lib):
     g4 = geom((4, 4, 4, 4))
     assert lib.lqcd_cshift(ctypes.byref(g4), a, b, 4, 1, 0, None) == -1
     assert lib.lqcd_cshift(ctypes.byref(g4), a, b, 0, 2, 0, None) == -1
+    # generic operator and its kernels: FP64 / FP32 only, no aliasing, mu / sign ranges
+    t1, t2 = ctypes.c_void_p(12288), ctypes.c_void_p(16384)
+    u = ctypes.c_void_p(20480)
+    assert lib.lqcd_dslash_generic(ctypes.byref(g4), a, b, u, t1, t2, 0, 2, 12, None) == -1
+    assert lib.lqcd_dslash_generic(ctypes.byref(g4), a, b, u, t1, t1, 0, 0, 18, None) == -1
+    assert lib.lqcd_dslash_generic(ctypes.byref(g4), a, a, u, t1, t2, 0, 0, 18, None) == -1
+    assert lib.lqcd_colour_mul(ctypes.byref(g4), a, b, u, 4, 0, 0, 18, None) == -1
+    assert lib.lqcd_spin_project(ctypes.byref(g4), a, b, 0, 2, 0, 0, None) == -1
+    assert lib.lqcd_spin_project(ctypes.byref(g4), a, a, 0, 1, 0, 0, None) == -1
+    # t decomposition: slices must be whole tiles; region 0 or 1; faces for region 1
+    assert lib.lqcd_face_bytes(ctypes.byref(g4), 0) == 0  # 4^4: 32 sites per slice
+    g8 = geom((8, 8, 8, 8))
+    assert lib.lqcd_face_bytes(ctypes.byref(g8), 0) == 256 * 6 * 16
+    assert lib.lqcd_face_bytes(ctypes.byref(g8), 2) == 256 * 6 * 8
+    assert lib.lqcd_hop_region(ctypes.byref(g8), 0, 2, a, b, None, u, t1, t2, 1.0, 0.0, 0, 0, 18,
+                               None) == -1
+    assert lib.lqcd_hop_region(ctypes.byref(g8), 0, 1, a, b, None, u, None, t2, 1.0, 0.0, 0, 0, 18,
+                               None) == -1
+    assert lib.lqcd_hop_region(ctypes.byref(g4), 0, 0, a, b, None, u, None, None, 1.0, 0.0, 0, 0,
+                               18, None) == -1
+    assert lib.lqcd_face_pack(ctypes.byref(g8), t1, t1, b, u, 0, 0, 0, 18, None) == -1
     # SU(3) product: binary16 is not a product precision
     assert lib.lqcd_su3_mul(ctypes.byref(g4), a, b, ctypes.c_void_p(12288), 0, 0, 2, 12, None) == -1
 

@@ -4,7 +4,8 @@ Raw link gradients and su(3) forces are compared with the FP64 oracle
 (FP64 <= 1e-13, FP32 <= 2e-6 relative); the autograd function is checked
 with torch.autograd.gradcheck on 2^4 and, on the 24^4 workload, with
 central finite differences (h = 1e-6, FP64) of S = |M psi|^2 on 64 random
-site entries and 64 random link entries.  The finite differences sum
+site entries and 64 random link entries, through the same 12-real forward
+that is differentiated.  The finite differences sum
 |phi(y)|^2 only over the sites a perturbation can change, which is the same
 difference of S without the cancellation of the full-lattice sum.
 """
@@ -16,7 +17,7 @@ import torch
 import lattice_inputs as LI
 import paper_2001_07557_amd as P
 from oracle import dirac, force, links, solver
-from tests.gpu_helpers import dev, f32, host, rel
+from tests.gpu_helpers import dev, f32, host, rel, site_rel
 
 pytestmark = pytest.mark.gpu
 
@@ -44,20 +45,35 @@ def test_force_kernel_vs_oracle(dims, bc, prec, link):
     F = force.su3_force(G, Ur)
     got_g = host(P.unpack_gauge(P.fermion_force(Xf, Yf, Uf, c0, mode=1)))
     assert rel(got_g, G) < tol
+    assert site_rel(got_g, G, per=9) < tol
     out = P.fermion_force(Xf, Yf, Uf, c0, mode=0)
-    assert rel(host(P.unpack_gauge(out)), F) < tol
+    got_f = host(P.unpack_gauge(out))
+    assert rel(got_f, F) < tol
+    assert site_rel(got_f, F, per=9) < tol
     # accumulate adds to the existing field
     P.fermion_force(Xf, Yf, Uf, c0, mode=0, out=out, accumulate=True)
     assert rel(host(P.unpack_gauge(out)), 2 * F) < tol
+    if link == 12:
+        # the gradient carried onto the stored rows 0 and 1 (row 2 zero)
+        rows = Ur if prec == P.F64 else f32(U)
+        want = force.rows01_gradient(G, rows)
+        got = host(P.unpack_gauge(P.fermion_force(Xf, Yf, Uf, c0, mode=2)))
+        assert rel(got, want) < tol
+        assert site_rel(got, want, per=9) < tol
 
 
-def test_autograd_gradcheck_2x4():
+@pytest.mark.parametrize("link", [P.LINK18, P.LINK12])
+def test_autograd_gradcheck_2x4(link):
+    """gradcheck perturbs every real entry of U: with 12-real links the
+    operator reads rows 0 and 1 only and rebuilds row 2, so the gradient
+    with respect to the stored row 2 is zero and rows 0, 1 carry the chain
+    through the rebuild."""
     dims = (2, 2, 2, 2)
     lat = P.Lattice(dims)
     U, psi = LI.workload_fields(32, dims)
     tpsi = dev(psi).requires_grad_(True)
     tU = dev(U).requires_grad_(True)
-    f = lambda a, b: P.wilson_matrix(a, b, KAPPA, lat, P.F64, P.LINK18)  # noqa: E731
+    f = lambda a, b: P.wilson_matrix(a, b, KAPPA, lat, P.F64, link)  # noqa: E731
     assert torch.autograd.gradcheck(f, (tpsi, tU), eps=1e-6, atol=1e-8, rtol=1e-7)
 
 
@@ -74,10 +90,16 @@ def test_autograd_vjp_vs_oracle(prec, link):
     phi.backward(dev(g).to(tdt))
     want_phi = dirac.wilson(psi, U, KAPPA)
     want_gpsi, want_gU = force.vjp(psi, U, KAPPA, g)
+    if link == 12:
+        want_gU = force.rows01_gradient(want_gU, U)
     tol = 2e-6 if prec == P.F32 else 1e-13
     assert rel(host(phi).astype(np.complex128), want_phi) < tol
     assert rel(host(tpsi.grad).astype(np.complex128), want_gpsi) < tol
     assert rel(host(tU.grad).astype(np.complex128), want_gU) < tol
+    if prec == P.F32:
+        assert site_rel(host(phi), want_phi) < tol
+        assert site_rel(host(tpsi.grad), want_gpsi) < tol
+        assert site_rel(host(tU.grad), want_gU, per=9) < tol
 
 
 def test_autograd_su3_force_mode():
@@ -125,22 +147,26 @@ def test_differentiated_24x4(prec):
     (phi.abs() ** 2).sum().backward()
     gpsi = host(tpsi.grad).astype(np.complex128)
     gU = host(tU.grad).astype(np.complex128)
-    # against the oracle gradient (FP64 oracle on FP64 inputs for both precisions)
+    # against the oracle gradient (FP64 oracle on FP64 inputs for both
+    # precisions; 12-real links: the gradient on the stored rows 0 and 1)
     want_gpsi = force.grad_psi_norm(psi, U, KAPPA)
-    want_gU = force.grad_links_norm(psi, U, KAPPA)
+    want_gU = force.rows01_gradient(force.grad_links_norm(psi, U, KAPPA), U)
     tol = 2e-6 if prec == P.F32 else 1e-13
     assert rel(gpsi, want_gpsi) < tol
     assert rel(gU, want_gU) < tol
     if prec != P.F64:
+        assert site_rel(gpsi, want_gpsi) < tol
+        assert site_rel(gU, want_gU, per=9) < tol
         return
-    # central finite differences on the GPU forward, h = 1e-6
+    # central finite differences on the same GPU forward (12-real links),
+    # h = 1e-6; entries of the stored row 2 have zero gradient
     rng = LI.fd_rng(4)
     h = 1e-6
     Ut = dev(U)
 
     def phi_of(ps, uu):
         with torch.no_grad():
-            return host(P.wilson_matrix(ps, uu, KAPPA, lat, P.F64, P.LINK18))
+            return host(P.wilson_matrix(ps, uu, KAPPA, lat, P.F64, P.LINK12))
 
     worst = 0.0
     for _ in range(64):

@@ -8,7 +8,7 @@ import lattice_inputs as LI
 import paper_2001_07557_amd as P
 from oracle import dirac, links
 from oracle.shift import split_rotate
-from tests.gpu_helpers import dev, f32, host, rel
+from tests.gpu_helpers import dev, f32, host, rel, site_rel
 
 pytestmark = pytest.mark.gpu
 
@@ -49,6 +49,102 @@ def test_dslash_composed_from_shifts():
         P.cshift(sh, P.pack_spinor(lat, dev(upsi), P.F64), mu, -1)
         total += dirac.spin_mul(dirac.ONE4 + dirac.GAMMA[mu], host(P.unpack_spinor(sh)))
     assert rel(host(P.unpack_spinor(fused)), total) < 1e-14
+
+
+@pytest.mark.parametrize("prec", [P.F64, P.F32])
+def test_colour_mul_and_spin_project(prec):
+    """The two per-site kernels of the generic operator against the
+    oracle's colour and spin products."""
+    dims = (6, 4, 2, 6)
+    lat = P.Lattice(dims, (1, 1, 1, -1))
+    U, psi = LI.workload_fields(44, dims)
+    tdt = torch.complex64 if prec == P.F32 else torch.complex128
+    Ur, pr = (f32(U), f32(psi)) if prec == P.F32 else (U, psi)
+    tol = 2e-6 if prec == P.F32 else 1e-15
+    Uf = P.pack_gauge(lat, dev(U).to(tdt), prec, 18)
+    src = P.pack_spinor(lat, dev(psi).to(tdt), prec)
+    out = P.new_spinor(lat, prec, P.FULL)
+    for mu in range(4):
+        for adj in (False, True):
+            P.colour_mul(out, src, Uf, mu, adjoint=adj)
+            u = Ur[..., mu, :, :]
+            want = dirac.colour_mul(dirac.dagger3(u) if adj else u, pr)
+            got = host(P.unpack_spinor(out))
+            assert rel(got, want) < tol
+            assert site_rel(got, want) < tol
+        for sign in (1, -1):
+            proj = dirac.ONE4 + sign * dirac.GAMMA[mu]
+            # each entry is one addition of two stored values (times units),
+            # rounded once to the storage precision
+            want = dirac.spin_mul(proj, pr)
+            if prec == P.F32:
+                want = f32(want)
+            P.spin_project(out, src, mu, sign, accumulate=False)
+            assert np.array_equal(host(P.unpack_spinor(out)), want)
+            P.spin_project(out, src, mu, sign, accumulate=True)
+            assert np.array_equal(host(P.unpack_spinor(out)), 2 * want)
+
+
+@pytest.mark.parametrize("dims,bc", [((4, 4, 4, 4), (1, 1, 1, -1)), ((6, 4, 2, 6), (-1, 1, 1, -1)),
+                                     ((2, 2, 2, 2), (1, 1, 1, -1)), ((8, 6, 4, 10), (-1, 1, -1, 1))])
+@pytest.mark.parametrize("prec,link", [(P.F64, 18), (P.F64, 12), (P.F32, 18), (P.F32, 12)])
+def test_generic_dslash_vs_oracle(dims, bc, prec, link):
+    """D_hop and its adjoint composed on the GPU from shifts, colour
+    products and projections (24 launches) against the oracle, and against
+    the fused kernel."""
+    lat = P.Lattice(dims, bc)
+    U, psi = LI.workload_fields(45, dims)
+    tdt = torch.complex64 if prec == P.F32 else torch.complex128
+    if prec == P.F32:
+        Ur, pr, tol = f32(U), f32(psi), 2e-6
+        if link == 12:
+            Ur = links.reconstruct(links.compress(Ur))
+    else:
+        Ur, pr, tol = U, psi, 1e-13
+    Uf = P.pack_gauge(lat, dev(U).to(tdt), prec, link)
+    src = P.pack_spinor(lat, dev(psi).to(tdt), prec)
+    out, fused = P.new_spinor(lat, prec, P.FULL), P.new_spinor(lat, prec, P.FULL)
+    t1, t2 = P.new_spinor(lat, prec, P.FULL), P.new_spinor(lat, prec, P.FULL)
+    for dag in (False, True):
+        P.dslash_generic(out, src, Uf, t1, t2, dagger=dag)
+        got = host(P.unpack_spinor(out))
+        want = dirac.dhop(pr, Ur, bc, dagger=dag)
+        assert rel(got, want) < tol
+        if prec == P.F32:
+            assert site_rel(got, want) < tol
+        P.dslash(fused, src, Uf, dagger=dag)
+        assert rel(got, host(P.unpack_spinor(fused))) < tol
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("prec,link", [(P.F64, 18), (P.F32, 12)])
+def test_generic_dslash_32x4_sampled(prec, link):
+    """The generic operator at the size the benchmark times it (32^4)
+    against the oracle at 256 sampled sites including every corner."""
+    from tests.gpu_helpers import DeviceGather
+    dims = (32, 32, 32, 32)
+    lat = P.Lattice(dims)
+    Ud, psid = LI.workload_fields_device(46, dims, "cuda")
+    tdt = torch.complex64 if prec == P.F32 else torch.complex128
+    tol = 2e-6 if prec == P.F32 else 1e-13
+    Uf = P.pack_gauge(lat, Ud.to(tdt), prec, link)
+    src = P.pack_spinor(lat, psid.to(tdt), prec)
+    out = P.new_spinor(lat, prec, P.FULL)
+    t1, t2 = P.new_spinor(lat, prec, P.FULL), P.new_spinor(lat, prec, P.FULL)
+    Uc = P.unpack_gauge(Uf)  # the links the kernels apply (row 2 rebuilt)
+    pc = P.unpack_spinor(src)
+    rng = np.random.default_rng(47)
+    corners = np.array([[x, y, z, t] for x in (0, 31) for y in (0, 31) for z in (0, 31)
+                        for t in (0, 31)])
+    for dag in (False, True):
+        P.dslash_generic(out, src, Uf, t1, t2, dagger=dag)
+        res = P.unpack_spinor(out)
+        sites = np.concatenate([corners, np.stack([rng.integers(0, 32, 240) for _ in dims], 1)])
+        want = dirac.dhop_at(DeviceGather(pc), DeviceGather(Uc), sites, dagger=dag)
+        got = res[sites[:, 3], sites[:, 2], sites[:, 1], sites[:, 0]].cpu().numpy()
+        assert rel(got, want) < tol
+        if prec == P.F32:
+            assert site_rel(got, want) < tol
 
 
 @pytest.mark.parametrize("vl,s,r", [(64, 1, 5), (64, 4, 3), (32, 2, 7), (16, 8, 1), (8, 8, 0),
@@ -95,6 +191,8 @@ def test_su3_product(prec, link, adj):
     got = host(P.unpack_gauge(Wf))
     tol = 1e-14 if prec == P.F64 else 2e-6
     assert rel(got, want) < tol
+    if prec == P.F32:
+        assert site_rel(got, want, per=9) < tol
     # in place: W may alias U
     P.su3_mul(Uf, Uf, Vf, *adj)
     assert rel(host(P.unpack_gauge(Uf)), want) < tol
@@ -118,3 +216,4 @@ def test_su3_product_48x3x96_sampled():
     Vr = P.unpack_gauge(Vf, torch.complex64)[idx].cpu().numpy().astype(np.complex128)
     Wr = P.unpack_gauge(Wf, torch.complex64)[idx].cpu().numpy().astype(np.complex128)
     assert rel(Wr, links.su3_product(Ur, Vr)) < 2e-6
+    assert site_rel(Wr, links.su3_product(Ur, Vr), per=9) < 2e-6

@@ -110,6 +110,25 @@ def test_cg_true_residual_by_oracle(inner, dims):
     assert rel(x, xo) < 1e-8
 
 
+@pytest.mark.parametrize("inner", [(P.F32, 12), (P.F16, 12)])
+@pytest.mark.parametrize("every", [3, 7, 16])
+def test_cg_scheduled_reliable_updates(inner, every):
+    """The FP64 reliable update taken on its schedule (every `every` inner
+    iterations, below the iteration count, so the scheduled path and the
+    restart that keeps p both run), besides the drift and tolerance
+    triggers; the oracle recomputes the true residual and the solution."""
+    dims = (8, 8, 8, 8)
+    U, b, x, st = solve_case(dims, 23, *inner, reliable_every=every)
+    assert st.status == 0
+    assert st.iterations > every
+    assert st.reliable_updates >= st.iterations // every
+    res = solver.true_residual(x, dirac.project(b, 0), U, KAPPA)
+    assert res <= 1.0001e-10
+    assert abs(res - st.true_residual) <= 1e-3 * st.true_residual + 1e-15
+    xo, _, _ = solver.solve_normal(dirac.project(b, 0), U, KAPPA, tol=1e-12)
+    assert rel(x, xo) < 1e-8
+
+
 def test_cg_free_field_plane_wave():
     dims = (8, 8, 8, 8)
     U = np.zeros(LI.links_shape(dims), dtype=np.complex128)
@@ -197,3 +216,19 @@ def test_cg_32x4_smoothed_mixed_vs_fp64():
         print(f"32^4 {name}: relative difference to the FP64 solution "
               f"{rel(sols[name], sols['f64']):.3e}", flush=True)
         assert rel(sols[name], sols["f64"]) < 1e-7
+    # the scheduled FP64 reliable update below the iteration count
+    for name, (prec, link) in {"f32": (P.F32, 12), "f16": (P.F16, 12)}.items():
+        U_lo = P.pack_gauge(lat, Ud.to(torch.complex64) if prec == P.F32 else Ud, prec, link)
+        for every in (7, 16):
+            x = P.new_spinor(lat, P.F64, P.EVEN)
+            st = P.cg_solve(x, b, U_hi, U_lo, KAPPA, tol=1e-10, maxiter=20000,
+                            reliable_every=every)
+            xs = host(P.unpack_spinor(x))
+            r = b_host - dirac.normal_op(xs, U_host, KAPPA)
+            ores = np.sqrt(np.vdot(r, r).real / bb)
+            print(f"32^4 {name} reliable every {every}: {st.iterations} iterations, "
+                  f"{st.reliable_updates} reliable updates, oracle residual {ores:.3e}", flush=True)
+            assert st.status == 0 and st.iterations > every
+            assert st.reliable_updates >= st.iterations // every
+            assert ores <= 1.0001e-10
+            assert rel(xs, sols["f64"]) < 1e-7

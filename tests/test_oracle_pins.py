@@ -386,6 +386,38 @@ def test_raw_link_gradient_finite_differences():
             assert abs(fd - an) <= 1e-6 * max(1.0, abs(an))
 
 
+def test_rows01_gradient_finite_differences():
+    """Gradient with respect to the stored rows 0 and 1 of 12-real links
+    (the operator applies V = (row0, row1, conj(row0 x row1))) against
+    central differences of |M[V] psi|^2 in those entries; the stored row 2 is
+    never read, so its gradient is zero.  The rows are generic complex rows,
+    not SU(3), so both cross-product terms of the chain rule matter."""
+    dims = (4, 4, 4, 4)
+    U, psi = LI.workload_fields(17, dims)
+    rng = LI.fd_rng(17)
+    R = U + 0.3 * (rng.standard_normal(U.shape) + 1j * rng.standard_normal(U.shape))
+
+    def S(rows):
+        return force.action_norm(psi, links.reconstruct(rows[..., :2, :]), KAPPA, BC)
+
+    V = links.reconstruct(R[..., :2, :])
+    G12 = force.rows01_gradient(force.grad_links_norm(psi, V, KAPPA, BC), R)
+    h = 1e-5
+    picks = [(dims[3] - 1, 0, 0, 0, 3), (0, 0, 0, dims[0] - 1, 0)]
+    picks += [tuple(int(rng.integers(0, n)) for n in R.shape[:5]) for _ in range(8)]
+    for site_mu in picks:
+        for i in range(3):
+            j = int(rng.integers(0, 3))
+            idx = site_mu + (i, j)
+            for part in (1.0, 1j):
+                rp = R.copy(); rp[idx] += part * h
+                rm = R.copy(); rm[idx] -= part * h
+                fd = (S(rp) - S(rm)) / (2 * h)
+                an = G12[idx].real if part == 1.0 else G12[idx].imag
+                assert abs(fd - an) <= 1e-6 * max(1.0, abs(an))
+    assert np.all(G12[..., 2, :] == 0)
+
+
 def test_su3_force_finite_differences():
     dims = (4, 4, 4, 4)
     U, psi = LI.workload_fields(11, dims)
@@ -487,6 +519,58 @@ def test_fp16_spinor_storage_bounds():
     err = np.maximum(np.abs(q.real - psi.real), np.abs(q.imag - psi.imag)).max(axis=(-1, -2))
     # binary16 has an 11-bit significand: half-ulp of values <= 1 is <= 2^-12
     assert np.all(err <= scale * (2.0 ** -11))
+
+
+# An FP32 pair (x, s) for which binary16(x * fl32(1/s)) and binary16(x / s)
+# differ (found by a seeded search over IEEE arithmetic; the test re-checks it).
+F16_X_BITS, F16_S_BITS = 1063116027, 1073232281
+
+
+def on_site_grid(values, scale):
+    """True where value == fl32(h * scale) for the binary16 number h nearest
+    value / scale, |h| <= 1: the value lies on the site's scaled binary16 grid."""
+    s32 = np.asarray(scale, dtype=np.float32)[..., None, None]
+    out = np.ones(values.shape, dtype=bool)
+    for part in (values.real, values.imag):
+        v32 = part.astype(np.float32)
+        h = (v32.astype(np.float64) / s32.astype(np.float64)).astype(np.float16)
+        back = (h.astype(np.float32) * s32).astype(np.float32)
+        out &= (back == v32) & (np.abs(h.astype(np.float64)) <= 1.0) & (v32.astype(np.float64) == part)
+    return out
+
+
+def test_fp16_spinor_storage_rule():
+    """binary16 spinor storage is a reading (the paper has no reduced
+    precision): one FP32 scale per site, the largest |real| among all 24 reals
+    of the site, and stored = binary16(real x fl32(1/scale)).  Pinned by
+    properties that do not reuse the oracle's formula: every stored value lies
+    on its site's scaled binary16 grid (a per-spin scale puts the small spins
+    elsewhere), the site's largest entry comes back exactly, and for a
+    constructed entry the reciprocal multiply and a division round to
+    different binary16 numbers."""
+    rng = np.random.default_rng(61)
+    dims = (2, 2, 2, 4)
+    psi = LI.gaussian_spinor(rng, dims)
+    psi[..., 0, :] *= 100.0   # spin 0 sets the site scale
+    psi[..., 3, :] *= 1e-3    # spin 3 far below it
+    q = links.round_f16_spinor(psi)
+    re32, im32 = psi.real.astype(np.float32), psi.imag.astype(np.float32)
+    scale = np.maximum(np.abs(re32).max(axis=(-1, -2)), np.abs(im32).max(axis=(-1, -2)))
+    assert np.all(on_site_grid(q, scale))
+    big = np.maximum(np.abs(q.real).max(axis=(-1, -2)), np.abs(q.imag).max(axis=(-1, -2)))
+    assert np.array_equal(big, scale.astype(np.float64))
+    # multiply by the rounded reciprocal, not divide
+    x = np.array([F16_X_BITS], dtype=np.uint32).view(np.float32)[0]
+    s = np.array([F16_S_BITS], dtype=np.uint32).view(np.float32)[0]
+    mul = np.float16(np.float32(x * np.float32(np.float32(1) / s)))
+    div = np.float16(np.float32(x / s))
+    assert mul != div
+    site = np.zeros((1, 1, 1, 1, 4, 3), dtype=np.complex128)
+    site[..., 0, 0] = float(s)
+    site[..., 2, 1] = 1j * float(x)
+    got = links.round_f16_spinor(site)[0, 0, 0, 0, 2, 1].imag
+    assert got == float(np.float32(np.float32(mul) * s))
+    assert got != float(np.float32(np.float32(div) * s))
 
 
 # ----------------------------------------------------------------------------
