@@ -23,7 +23,9 @@
  *  - Every pointer named as a field (spinor, gauge, force, workspace) is
  *    DEVICE memory owned by the caller.  The library never allocates, frees
  *    or retains device memory and keeps no global state besides the HIP
- *    module.  Host pointers are named so explicitly (stats, result).
+ *    module, whose one static device array (the scratch of
+ *    lqcd_dot_noalloc) comes with it.  Host pointers are named so
+ *    explicitly (stats, result).
  *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).
  *    Every call is enqueued on it and returns without waiting, except where
  *    a function states that it synchronises the stream.
@@ -62,7 +64,8 @@ extern "C" {
 #define LQCD_EHIP     -2   /* HIP launch or runtime error */
 #define LQCD_ENOCONV  -3   /* solver hit maxiter; x holds the last iterate */
 #define LQCD_ENAN     -4   /* non-finite residual detected */
-#define LQCD_ESMALL   -5   /* workspace smaller than the size query returned */
+#define LQCD_ESMALL   -5   /* workspace smaller than the size query returned, or a
+                              field too large for the static scratch of lqcd_dot_noalloc */
 
 /* storage precisions: arithmetic is FP64 for LQCD_F64 and FP32 otherwise */
 #define LQCD_F64   0
@@ -221,6 +224,21 @@ size_t lqcd_reduce_workspace_bytes(const lqcd_geom_t *g, int subset);
    in a fixed order: bitwise reproducible.  Synchronises the stream. */
 int lqcd_dot(const lqcd_geom_t *g, int subset, const void *a, const void *b, int prec,
              void *workspace, double *result, void *stream);
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): lqcd_dot
+ * without the workspace argument.  The block partials live in a static
+ * device array of the library (1 MiB per GPU, held until the process ends),
+ * so the call allocates nothing; arguments, result and synchronisation as for
+ * lqcd_dot.  Fields of more than LQCD_DOT_NOALLOC_MAX_SITES sites in the
+ * subset (V/2 for EVEN/ODD, V for FULL) return LQCD_ESMALL before any work
+ * is enqueued.  Every call on one GPU shares that GPU's array: calls that
+ * overlap on one GPU (two host threads, or two streams without ordering)
+ * race and may return wrong sums.  A call leaves nothing behind that a later
+ * call depends on. */
+#define LQCD_DOT_NOALLOC_MAX_SITES 16776960
+int lqcd_dot_noalloc(const lqcd_geom_t *g, int subset, const void *a, const void *b, int prec,
+                     double *result, void *stream);
 
 /* *result = ||a||^2 (host double); same reduction and synchronisation. */
 int lqcd_norm2(const lqcd_geom_t *g, int subset, const void *a, int prec,

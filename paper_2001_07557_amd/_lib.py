@@ -69,6 +69,8 @@ SIGNATURES = {
     "lqcd_reduce_workspace_bytes": (c_size_t, [G, c_int]),
     "lqcd_dot": (c_int, [G, c_int, c_void_p, c_void_p, c_int, c_void_p,
                          ctypes.POINTER(c_double), c_void_p]),
+    "lqcd_dot_noalloc": (c_int, [G, c_int, c_void_p, c_void_p, c_int, ctypes.POINTER(c_double),
+                                 c_void_p]),
     "lqcd_norm2": (c_int, [G, c_int, c_void_p, c_int, c_void_p, ctypes.POINTER(c_double),
                            c_void_p]),
     "lqcd_axpby": (c_int, [G, c_int, c_double, c_void_p, c_double, c_void_p, c_int, c_void_p]),

@@ -3,6 +3,8 @@
 // up), y = a x + b y, and precision conversion.  One thread per site; a
 // FULL field is the even half followed by the odd half.
 
+#include <mutex>
+
 #include "lqcd_internal.h"
 #include "reduce.h"
 #include "blas.h"
@@ -222,6 +224,66 @@ extern "C" int lqcd_dot(const lqcd_geom_t *g, int subset, const void *a, const v
                         void *workspace, double *result, void *stream) {
     if (!b) return LQCD_EINVAL;
     return reduce_entry(g, subset, a, b, prec, workspace, result, stream);
+}
+
+// ---------------------------------------------------------------------------
+// allocation-free inner product: the block partials live in a static device
+// array instead of caller workspace
+// ---------------------------------------------------------------------------
+
+// Doubles of the static scratch: two per reduction block plus the two-double
+// result, 1 MiB in all (every GPU the library runs on keeps its own copy until
+// the process ends).
+constexpr int64_t NOALLOC_DOUBLES = (int64_t)1 << 17;
+static __device__ __align__(256) double scratch[NOALLOC_DOUBLES];
+
+constexpr int MAX_DEVICES = 64;
+static std::mutex scratch_mutex;
+static double *scratch_ptr[MAX_DEVICES] = {};
+
+// Device address of this GPU's copy of `scratch`, looked up once per device
+// with that device current (the host-side name of the array is not a device
+// address and must never reach a kernel).
+static int scratch_address(double **out) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) {
+        set_hip_error(e);
+        return LQCD_EHIP;
+    }
+    if (dev < 0 || dev >= MAX_DEVICES) return LQCD_EINVAL;
+    std::lock_guard<std::mutex> lock(scratch_mutex);
+    if (!scratch_ptr[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) {
+            set_hip_error(e != hipSuccess ? e : hipErrorInvalidSymbol);
+            return LQCD_EHIP;
+        }
+        scratch_ptr[dev] = (double *)p;
+    }
+    *out = scratch_ptr[dev];
+    return LQCD_OK;
+}
+
+// two doubles per block of RED_BLOCK sites, plus the result
+static_assert((NOALLOC_DOUBLES - 2) / 2 * RED_BLOCK == LQCD_DOT_NOALLOC_MAX_SITES,
+              "the header's site limit matches the static scratch");
+
+extern "C" int lqcd_dot_noalloc(const lqcd_geom_t *gg, int subset, const void *a, const void *b,
+                                int prec, double *result, void *stream) {
+    Geom g;
+    const int nh = subset_halves(subset);
+    if (!b || !make_geom(gg, &g) || !nh || !valid_prec(prec)) return LQCD_EINVAL;
+    if (!al16(a) || !al16(b) || !result) return LQCD_EINVAL;
+    const int64_t nb = reduce_blocks(g, nh);
+    if (2 * nb + 2 > NOALLOC_DOUBLES) return LQCD_ESMALL;
+    double *ws = nullptr;
+    const int rc = scratch_address(&ws);
+    if (rc) return rc;
+    // every partial is written by the reduction before the final sum reads
+    // it, so nothing left over from an earlier call needs clearing
+    return reduce_entry(gg, subset, a, b, prec, ws, result, stream);
 }
 
 extern "C" int lqcd_norm2(const lqcd_geom_t *g, int subset, const void *a, int prec,

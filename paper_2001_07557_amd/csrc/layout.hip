@@ -153,7 +153,7 @@ extern "C" const char *lqcd_strerror(int status) {
         case LQCD_EHIP: return "HIP runtime or launch error";
         case LQCD_ENOCONV: return "solver did not converge within maxiter";
         case LQCD_ENAN: return "non-finite residual";
-        case LQCD_ESMALL: return "workspace too small";
+        case LQCD_ESMALL: return "workspace (or static scratch) too small";
         default: return "unknown status";
     }
 }

@@ -108,6 +108,13 @@ def test_invalid_arguments_rejected(lib):
     assert st.status == -5
     # reductions: NULL result pointer
     assert lib.lqcd_norm2(ctypes.byref(g), 0, a, 0, ws, None, None) == -1
+    # allocation-free inner product: NULL operand, and a field larger than its
+    # static scratch (64^4 sites, full field) is refused before any HIP call
+    res = (ctypes.c_double * 2)()
+    assert lib.lqcd_dot_noalloc(ctypes.byref(g), 2, a, None, 0, res, None) == -1
+    assert lib.lqcd_dot_noalloc(ctypes.byref(g), 2, a, b, 0, None, None) == -1
+    big = geom((64, 64, 64, 64))
+    assert lib.lqcd_dot_noalloc(ctypes.byref(big), 2, a, b, 1, res, None) == -5
     # force: mode 2 (rows 0, 1 of 12-real links) needs 12-real links
     assert lib.lqcd_fermion_force(ctypes.byref(g), a, b, ctypes.c_void_p(12288), u, 1.0, 2, 0, 0,
                                   18, None) == -1
