@@ -169,7 +169,11 @@ def main():
                          "48^3x96) and the copy-bandwidth measurement")
     ap.add_argument("--no-grad", action="store_true",
                     help="skip the forward / backward timing of the differentiated operator")
-    ap.add_argument("--grad-lattice", default="24,24,24,24")
+    ap.add_argument("--grad-lattice", default="24,24,24,24",
+                    help="lattice(s) of the gradient section, ';'-separated")
+    ap.add_argument("--sweep-lattices", default="24,24,24,24;32,32,32,32;48,48,48,96;48,48,48,12",
+                    help="';'-separated lattices of the sweep (the benchmark lattice from a "
+                         "rotating input pool always comes first)")
     ap.add_argument("--no-split", action="store_true",
                     help="skip the t-decomposition timing (face pack, exchange, interior, boundary)")
     ap.add_argument("--split-lattice", default="48,48,48,12")
@@ -250,7 +254,9 @@ def main():
 
     sweep = None
     if not args.no_sweep and not args.only:
-        sweep = run_sweep(P, LI, torch, lattice, dev)
+        sweep = run_sweep(P, LI, torch, lattice, dev,
+                          [tuple(int(v) for v in g.split(",")) for g in args.sweep_lattices.split(";")
+                           if g])
         if HEADLINE in variants:
             sweep["copy_same_bytes"] = copy_same_bytes(
                 P, torch, lattice, results[f"{HEADLINE[0]}-{HEADLINE[1]}"]["us_per_launch"])
@@ -263,7 +269,11 @@ def main():
         log("t-split section done")
     grad = None
     if not args.no_grad:
-        grad = run_grad(P, LI, torch, tuple(int(v) for v in args.grad_lattice.split(",")), dev)
+        lats = [tuple(int(v) for v in g.split(",")) for g in args.grad_lattice.split(";") if g]
+        grad = run_grad(P, LI, torch, lats[0], dev)
+        for extra in lats[1:]:
+            grad["x".join(map(str, extra))] = run_grad(P, LI, torch, extra, dev)
+            torch.cuda.empty_cache()
         torch.cuda.empty_cache()
         log("gradient section done")
 
@@ -432,7 +442,7 @@ def copy_same_bytes(P, torch, lattice, hop_us, apps=100, reps=5):
                     f"algorithmic bytes), {apps} alternating copies per graph"}
 
 
-def run_sweep(P, LI, torch, lattice, dev, apps=20, steps=5, warmup=2):
+def run_sweep(P, LI, torch, lattice, dev, lattices, apps=20, steps=5, warmup=2):
     """Every storage variant on the lattices the bandwidth claim is made on,
     the benchmark lattice again with a rotating pool of input copies larger
     than the 256 MB Infinity Cache (so its launches read HBM), and each
@@ -441,8 +451,7 @@ def run_sweep(P, LI, torch, lattice, dev, apps=20, steps=5, warmup=2):
     torch.cuda.empty_cache()
     out = {"copy": copy, "apps_per_step": apps, "steps": steps}
     # 48^3x12 is one GPU's share of 48^3x96 split eight ways in t
-    cases = [(lattice, "pool")] + [(d, "plain") for d in ((24, 24, 24, 24), (32, 32, 32, 32),
-                                                           (48, 48, 48, 96), (48, 48, 48, 12))]
+    cases = [(lattice, "pool")] + [(d, "plain") for d in lattices]
     for dims, kind in cases:
         U, psi = LI.workload_fields_device(1, dims, dev)
         lat = P.Lattice(dims)

@@ -277,13 +277,16 @@ size_t lqcd_cg_workspace_bytes(const lqcd_geom_t *g, int inner_prec, int inner_l
  *   search direction; it is taken every `reliable_every` iterations (0 =
  *   never on a schedule), whenever the inner residual has fallen since the
  *   last update by 1000x (FP32 inner) or 10x (F16 inner), beyond which the
- *   inner recurrence is not trusted,
- *   and when the inner residual reaches tol.  The solve stops when
- *   ||b - A x|| / ||b|| <= tol in FP64.  The host reads the inner residual
- *   every 10 iterations while the tolerance is far and every iteration once
- *   the decay so far puts it within reach, so `iterations` is the first
- *   iteration whose inner residual reached tol (when the FP64 check then
- *   confirms it).
+ *   inner recurrence is not trusted (put off, by at most a further 100x
+ *   fall, while the decay so far puts the tolerance within ten iterations,
+ *   when the final update comes first),
+ *   and when the inner residual reaches tol (tol/2 for FP32 and F16 inner
+ *   iterations, whose recurrence residual runs ahead of the true one).  The
+ *   solve stops when ||b - A x|| / ||b|| <= tol in FP64.  The host reads the
+ *   inner residual every 10 iterations while the tolerance is far and every
+ *   iteration once the decay so far puts it within reach, so `iterations` is
+ *   the first iteration whose inner residual reached that threshold (when the
+ *   FP64 check then confirms it).
  *   workspace: device memory of lqcd_cg_workspace_bytes() bytes.
  *   stats: host struct filled on return (may be NULL).
  * Synchronises the stream.  Returns LQCD_ENOCONV after maxiter inner

@@ -11,8 +11,9 @@
 // is near, so the solve stops at the first iteration that reaches it.
 //
 // Per iteration: 4 hop kernels (the second also produces |Mhat p|^2 = <p, A p>
-// block partials), one fused x += a p, r -= a Ap, |r|^2 kernel, p = r + b p,
-// and two single-block kernels that finish the sums and form alpha, beta.
+// block partials; the fourth does x += a p, r -= a Ap and the |r|^2 partials
+// in its epilogue, so Ap is never stored), p = r + b p, and two single-block
+// kernels that finish the sums and form alpha, beta.
 
 #include <chrono>
 #include <cmath>
@@ -35,6 +36,12 @@ constexpr int CHECK_EVERY = 10;
 // need it only at the end.
 constexpr double DELTA_F16 = 0.1;
 constexpr double DELTA_F32 = 1e-3;
+// A reduced-precision recurrence residual runs ahead of the true one, so the
+// final reliable update is taken when it reaches tol / 2 rather than tol
+// (squared: 0.25): an update taken when the recurrence first touches tol
+// finds the true residual still just above it and costs a second FP64 update
+// a few iterations later.
+constexpr double INNER_MARGIN2 = 0.25;
 
 enum { S_RR = 0, S_PAP, S_ALPHA, S_RROLD, S_BETA, S_OUT, S_COUNT = 16 };
 enum { OP_ALPHA = 0, OP_RRNEW, OP_RESET, OP_SUM, OP_SETRR };
@@ -79,36 +86,6 @@ __global__ __launch_bounds__(SCALAR_BLOCK) void cg_scalar_k(const double *partia
             sc[S_OUT] = s;
         }
     }
-}
-
-// xs += alpha p; rs -= alpha Ap; per-block |rs|^2.
-template <int P>
-__global__ __launch_bounds__(CG_BLOCK) void cg_update_k(char *xs, char *rs, const char *p,
-                                                        const char *ap, const double *sc,
-                                                        int64_t vh, double *partial) {
-    using T = typename real_of<P>::type;
-    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    double acc[1] = {0.0};
-    if (s < vh) {
-        const T alpha = (T)sc[S_ALPHA];
-        cplx<T> vx[12], vr[12], vp[12], va[12];
-        load_spinor<P>(p, s, vp);
-        load_spinor<P>(ap, s, va);
-        load_spinor<P>(xs, s, vx);
-        load_spinor<P>(rs, s, vr);
-        T nr = 0;
-#pragma unroll
-        for (int k = 0; k < 12; ++k) {
-            vx[k] = {vx[k].re + alpha * vp[k].re, vx[k].im + alpha * vp[k].im};
-            vr[k] = {vr[k].re - alpha * va[k].re, vr[k].im - alpha * va[k].im};
-            nr += norm2(vr[k]);
-        }
-        store_spinor<P>(xs, s, vx);
-        store_spinor<P>(rs, s, vr);
-        acc[0] = (double)nr;
-    }
-    block_sum<1>(acc);
-    if (threadIdx.x == 0) partial[blockIdx.x] = acc[0];
 }
 
 // p = rs + beta p.
@@ -173,7 +150,7 @@ __global__ __launch_bounds__(CG_BLOCK) void cg_residual_k(char *r, const char *b
 // ---------------------------------------------------------------------------
 
 struct CGWork {
-    char *xs, *rs, *p, *ap, *te, *to;  // inner precision
+    char *xs, *rs, *p, *te, *to;      // inner precision
     char *r64, *te64, *to64;          // FP64
     double *partial;
     double *sc;
@@ -203,7 +180,6 @@ static CGWork cg_layout(const Geom &g, int prec, char *base) {
     w.xs = take(hb);
     w.rs = take(hb);
     w.p = take(hb);
-    w.ap = take(hb);
     w.te = take(hb);
     w.to = take(hb);
     w.r64 = take(hb64);
@@ -215,20 +191,36 @@ static CGWork cg_layout(const Geom &g, int prec, char *base) {
     return w;
 }
 
-// Iterations until the next host read of the inner residual: CHECK_EVERY
-// while the tolerance is far, fewer as the geometric decay between the last
-// two reads (rr0 at k0, rr1 at k1) says it is near, and one once it is
-// within about one iteration, so the solve stops at the first iteration
-// whose residual reaches it instead of up to CHECK_EVERY - 1 later.
-static int next_read_after(double rr0, int k0, double rr1, int k1, double target) {
-    if (!(rr1 > target) || k1 <= k0 || !(rr0 > 0.0) || !(rr1 < rr0)) {
-        return rr1 > target && rr1 < 100.0 * target ? 1 : CHECK_EVERY;
-    }
-    const double per_iter = std::log(rr1 / rr0) / (double)(k1 - k0);  // < 0
-    const double left = std::log(target / rr1) / per_iter;             // > 0
-    const double n = std::floor(0.7 * left);
-    return n < 1.0 ? 1 : n > CHECK_EVERY ? CHECK_EVERY : (int)n;
+// Iterations the inner residual rr still needs to reach target when log(rr)
+// falls by -rate per iteration (rate < 0; rate = 0: not known yet).
+static int iterations_left(double rr, double rate, double target) {
+    if (!(rr > target)) return 0;
+    if (!(rate < 0.0)) return 1 << 20;
+    const double n = std::ceil(std::log(target / rr) / rate);
+    return n > (double)(1 << 20) ? 1 << 20 : (int)n;
 }
+
+// Iterations until the next host read: CHECK_EVERY while the tolerance is
+// far, fewer as it nears, one once it is about an iteration away, so the
+// solve stops at the first iteration whose residual reaches it instead of up
+// to CHECK_EVERY - 1 later.
+static int read_gap(int left) {
+    const int n = (int)(0.7 * left);
+    return n < 1 ? 1 : n > CHECK_EVERY ? CHECK_EVERY : n;
+}
+
+// A drift-triggered reliable update is put off while the tolerance is
+// predicted this close (in iterations): the final update follows soon, and
+// reading the residual every iteration near the end would otherwise add an
+// FP64 update a few iterations before the last one (at 32^4 FP32 inner:
+// three updates instead of two).  It is put off only until the inner
+// residual has fallen DRIFT_HARD (squared: 1e-4, a further factor 100, about
+// the most that reads every ten iterations let it drift) below the drift
+// threshold: without that bound an 8^4 FP32-inner solve to 1e-12, whose
+// recurrence keeps predicting the end, took 300 iterations instead of
+// under 200.
+constexpr int DRIFT_DEFER = CHECK_EVERY;
+constexpr double DRIFT_HARD = 1e-4;
 
 struct Solver {
     Geom g;
@@ -241,8 +233,12 @@ struct Solver {
     CGWork w;
 
     int hop(int out_par, char *out, const char *in, const char *y, double alpha, bool dag, int pr,
-            int lk, const char *U_, double *partial) {
+            int lk, const char *U_, double *partial, char *cg_x = nullptr,
+            const char *cg_p = nullptr) {
         HopArgs a{};
+        a.cg_x = cg_x;
+        a.cg_p = cg_p;
+        a.cg_alpha = w.sc + S_ALPHA;
         a.g = g;
         a.U = U_;
         a.alpha = alpha;
@@ -253,6 +249,23 @@ struct Solver {
         a.y[out_par] = y;
         a.partial = partial;
         return hop_launch(a, pr, lk, dag, 1, st);
+    }
+
+    // One inner iteration's operator and update: te = Mhat p (with the
+    // <p, A p> = |Mhat p|^2 partials, summed into alpha), then
+    // Mhat^dag te = A p formed inside the last hop, which updates xs and rs
+    // and leaves the |rs|^2 partials.
+    int apply_a_update(int pr, int lk, const char *U_) {
+        const double k2 = -kappa * kappa;
+        int rc = hop(LQCD_ODD, w.to, w.p, nullptr, 1.0, false, pr, lk, U_, nullptr);
+        if (!rc) rc = hop(LQCD_EVEN, w.te, w.to, w.p, k2, false, pr, lk, U_, w.partial);
+        if (!rc) {
+            cg_scalar_k<OP_ALPHA><<<1, SCALAR_BLOCK, 0, st>>>(w.partial, hop_partials(g, 1), 1, w.sc);
+            rc = check_launch();
+        }
+        if (!rc) rc = hop(LQCD_ODD, w.to, w.te, nullptr, 1.0, true, pr, lk, U_, nullptr);
+        if (!rc) rc = hop(LQCD_EVEN, w.rs, w.to, w.te, k2, true, pr, lk, U_, w.partial, w.xs, w.p);
+        return rc;
     }
 
     // out = Mhat^dag Mhat x; the block partials of |Mhat x|^2 go to `partial`
@@ -357,16 +370,18 @@ struct Solver {
         double rr_ref = rr;  // true residual at the last reliable update
         const double delta = P == LQCD_F64 ? 0.0 : P == LQCD_F32 ? DELTA_F32 : DELTA_F16;
         const double drift = delta * delta;
-        // residual at the last host read, and the iteration of the next one
+        const double target_inner = P == LQCD_F64 ? target : INNER_MARGIN2 * target;
+        // residual at the last host read, the decay of log(rr) per iteration
+        // between the last two reads (kept across reliable updates), and the
+        // iteration of the next read
         int k_seen = 0;
         double rr_seen = rr;
+        double rate = 0.0;
         int next_read = CHECK_EVERY;
         while (true) {
-            rc = apply_a(P, link, U, w.p, w.ap, w.te, w.to, w.partial);
+            rc = apply_a_update(P, link, U);
             if (rc) return rc;
-            cg_scalar_k<OP_ALPHA><<<1, SCALAR_BLOCK, 0, st>>>(w.partial, hop_partials(g, 1), 1, w.sc);
-            cg_update_k<P><<<grid(), CG_BLOCK, 0, st>>>(w.xs, w.rs, w.p, w.ap, w.sc, g.vh, w.partial);
-            cg_scalar_k<OP_RRNEW><<<1, SCALAR_BLOCK, 0, st>>>(w.partial, nblk(), 1, w.sc);
+            cg_scalar_k<OP_RRNEW><<<1, SCALAR_BLOCK, 0, st>>>(w.partial, hop_partials(g, 1), 1, w.sc);
             rc = check_launch();
             if (rc) return rc;
             ++k;
@@ -378,8 +393,13 @@ struct Solver {
                     stats->iterations = k;
                     return LQCD_ENAN;
                 }
-                if (rr_it <= target || rr_it < drift * rr_ref) reliable = true;
-                next_read = k + next_read_after(rr_seen, k_seen, rr_it, k, target);
+                if (k > k_seen && rr_it > 0.0 && rr_it < rr_seen)
+                    rate = std::log(rr_it / rr_seen) / (double)(k - k_seen);
+                const int left = iterations_left(rr_it, rate, target_inner);
+                if (rr_it <= target_inner) reliable = true;
+                if (rr_it < drift * rr_ref && (left > DRIFT_DEFER || rr_it < DRIFT_HARD * drift * rr_ref))
+                    reliable = true;
+                next_read = k + read_gap(left);
                 rr_seen = rr_it;
                 k_seen = k;
             }
@@ -401,7 +421,7 @@ struct Solver {
                 if (rc) return rc;
                 rr_seen = rr;
                 k_seen = k;
-                next_read = k + next_read_after(rr_ref, k, rr, k, target);
+                next_read = k + read_gap(iterations_left(rr, rate, target_inner));
             }
             cg_direction_k<P><<<grid(), CG_BLOCK, 0, st>>>(w.p, w.rs, w.sc, g.vh);
         }

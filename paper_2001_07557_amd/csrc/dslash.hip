@@ -48,15 +48,36 @@ namespace lqcd {
 #ifndef LQCD_HOP_PAIRED
 #define LQCD_HOP_PAIRED 1
 #endif
-// extra LDS bytes per 4-way block (ablation switch): limits the blocks in
-// flight per CU, and with them the window of tiles an XCD's L2 must hold
+// Blocks in flight of the FP64 4-way kernel on large lattices.  With ~120
+// VGPRs four blocks fit a CU, so an XCD's 32 CUs keep 128 tiles in flight,
+// more than one t-slice of its z-slab, and the three input t-slices the
+// brick order relies on no longer fit its 4 MB L2 beside them.  From
+// V/2 >= 2^20 sites (48^3x96 and up) the launch adds LQCD_HOP_F64_LDS_EXTRA
+// bytes of dynamic LDS per block (36 + 18 KB: two blocks per CU).  Measured
+// in two sessions (fraction of 8 TB/s, four -> two blocks per CU): 48^3x96
+// FP64-18 68.6 -> 70.7 and 68.6 -> 69.5, FP64-12 65.6 -> 67.7 and 65.5 ->
+// 67.1, full-lattice FP64-18 M 4.39 -> 4.88 TB/s; at 32^4 FP64-18 78.4 ->
+// 79.8 and 78.3 -> 77.9, FP64-12 73.9 -> 72.7 and 73.8 -> 73.0 (not taken);
+// three blocks per CU +0.6 at 48^3x96, one block 57%; binary16 storage
+// (also 4-way) loses 8 points with it and keeps four.  LQCD_HOP_EXTRA_LDS
+// forces a value for every 4-way launch (ablations).
+#ifndef LQCD_HOP_F64_LDS_EXTRA
+#define LQCD_HOP_F64_LDS_EXTRA 18432
+#endif
+#ifndef LQCD_HOP_F64_LDS_MIN_LOG2
+#define LQCD_HOP_F64_LDS_MIN_LOG2 20
+#endif
 #ifndef LQCD_HOP_EXTRA_LDS
-#define LQCD_HOP_EXTRA_LDS 0
+#define LQCD_HOP_EXTRA_LDS -1
 #endif
 constexpr int64_t INFINITY_CACHE_BYTES = (int64_t)256 << 20;
 
-// Epilogue shared by both kernel shapes: out = alpha acc + beta y, optional |out|^2.
-template <int P, bool HASY, bool NORM, bool NT>
+// Epilogue shared by the kernel shapes: out = alpha acc + beta y; NORM = 1
+// also returns |out|^2 of the site; NORM = 2 (the solver's last hop, with a y
+// term) stores nothing of out = A p but updates the CG iterate in place,
+// x += c p and r -= c A p (c the device's CG alpha, r at a.out), and returns
+// |r|^2 of the site.
+template <int P, bool HASY, int NORM, bool NT>
 __device__ __forceinline__ double hop_epilogue(const HopArgs &a, int p, int64_t s,
                                                cplx<typename real_of<P>::type> acc[12]) {
     using T = typename real_of<P>::type;
@@ -72,8 +93,55 @@ __device__ __forceinline__ double hop_epilogue(const HopArgs &a, int p, int64_t 
 #pragma unroll
         for (int k = 0; k < 12; ++k) acc[k] = scale(alpha, acc[k]);
     }
+    if constexpr (NORM == 2 && P == LQCD_F64 && !LQCD_LAYOUT_AOS) {
+        // FP64: four words of p, x and r at a time, so that the three
+        // vectors are never live together (occupancy of the 4-way shape)
+        const T c = (T)*a.cg_alpha;
+        const int64_t toff = (s >> TILE_SHIFT) * spinor_tile_bytes(P);
+        const int lane = (int)(s & (TILE - 1));
+        v2d *xw = reinterpret_cast<v2d *>(a.cg_x + toff) + lane;
+        v2d *rw = reinterpret_cast<v2d *>(a.out[p] + toff) + lane;
+        const v2d *pw = reinterpret_cast<const v2d *>(a.cg_p + toff) + lane;
+        T nr = 0;
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+            cplx<T> vx[4], vr[4];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int k = 4 * q + j;
+                const v2d dp = pw[k * TILE], dx = xw[k * TILE], dr = rw[k * TILE];
+                vx[j] = {dx.x + c * dp.x, dx.y + c * dp.y};
+                vr[j] = {dr.x - c * acc[k].re, dr.y - c * acc[k].im};
+                nr += norm2(vr[j]);
+            }
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int k = 4 * q + j;
+                xw[k * TILE] = v2d{vx[j].re, vx[j].im};
+                rw[k * TILE] = v2d{vr[j].re, vr[j].im};
+            }
+            __builtin_amdgcn_sched_barrier(0);
+        }
+        return (double)nr;
+    } else if constexpr (NORM == 2) {
+        const T c = (T)*a.cg_alpha;
+        cplx<T> vx[12], vr[12], vp[12];
+        load_spinor<P>(a.cg_p, s, vp);
+        load_spinor<P>(a.cg_x, s, vx);
+        load_spinor<P>(a.out[p], s, vr);
+        T nr = 0;
+#pragma unroll
+        for (int k = 0; k < 12; ++k) {
+            vx[k] = {vx[k].re + c * vp[k].re, vx[k].im + c * vp[k].im};
+            vr[k] = {vr[k].re - c * acc[k].re, vr[k].im - c * acc[k].im};
+            nr += norm2(vr[k]);
+        }
+        store_spinor<P>(a.cg_x, s, vx);
+        store_spinor<P>(a.out[p], s, vr);
+        return (double)nr;
+    }
     double nrm = 0.0;
-    if constexpr (NORM) {
+    if constexpr (NORM == 1) {
         T t = 0;
 #pragma unroll
         for (int k = 0; k < 12; ++k) t += norm2(acc[k]);
@@ -84,7 +152,8 @@ __device__ __forceinline__ double hop_epilogue(const HopArgs &a, int p, int64_t 
 }
 
 // The five fields read first lie on the five 64-byte lines of the arguments.
-static_assert(sizeof(HopArgs) <= 5 * 64, "launch arguments span more than five lines");
+static_assert(offsetof(HopArgs, cg_x) <= 5 * 64 && sizeof(HopArgs) <= 6 * 64,
+              "the fields read first span five lines, the CG-update fields a sixth");
 static_assert(offsetof(HopArgs, bpp) / 64 == 0 &&
                   (offsetof(HopArgs, g) + offsetof(Geom, vh)) / 64 == 1 &&
                   (offsetof(HopArgs, g) + offsetof(Geom, dz) + offsetof(FastDiv, m)) / 64 == 2 &&
@@ -115,7 +184,7 @@ __device__ __forceinline__ int64_t hop_site_index(const HopArgs &a, int lane, in
 
 // 4-way shape: wave w computes both hops of direction w; waves 1..3 leave
 // their partial spinors in LDS and wave 0 adds them up.
-template <int P, int LK, bool DAG, bool HASY, bool NORM, int NTM, bool HALO>
+template <int P, int LK, bool DAG, bool HASY, int NORM, int NTM, bool HALO>
 __global__ __launch_bounds__(256) void hop4_kernel(HopArgs a) {
     using T = typename real_of<P>::type;
     __shared__ cplx<T> part[3][12][64];
@@ -166,7 +235,7 @@ __global__ __launch_bounds__(256) void hop4_kernel(HopArgs a) {
 // 1-way shape (ablation builds, LQCD_HOP_SHAPE_* = 1): one wave per block,
 // every thread computes all eight hops of its site in registers, no LDS.
 // The four directions are added in the 4-way shape's order.
-template <int P, int LK, bool DAG, bool HASY, bool NORM, int NTM, bool HALO>
+template <int P, int LK, bool DAG, bool HASY, int NORM, int NTM, bool HALO>
 __global__ __launch_bounds__(64) void hop1_kernel(HopArgs a) {
     using T = typename real_of<P>::type;
     const int lane = threadIdx.x & 63;
@@ -263,7 +332,7 @@ __device__ __forceinline__ void rebuild_row(const HopArgs &a, int p, int64_t s,
 // 8-way shape: wave w computes hop w (direction w/2, forward for even w) and
 // stages the two colour vectors of its multiplied half-spinor in LDS; wave 0
 // rebuilds the four spin rows from the eight staged half-spinors.
-template <int P, int LK, bool DAG, bool HASY, bool NORM, int NTM, bool ROWS, bool HALO>
+template <int P, int LK, bool DAG, bool HASY, int NORM, int NTM, bool ROWS, bool HALO>
 __global__ __launch_bounds__(512) void hop8_kernel(HopArgs a) {
     using T = typename real_of<P>::type;
     __shared__ cplx<T> chi[8][6][64];
@@ -339,7 +408,7 @@ constexpr int hop_shape(int prec) {
                                                                      : LQCD_HOP_SHAPE_F16;
 }
 
-template <int P, int LK, bool DAG, bool HASY, bool NORM, int NTM, bool HALO>
+template <int P, int LK, bool DAG, bool HASY, int NORM, int NTM, bool HALO>
 static void launch_halo(const HopArgs &a, dim3 grid, hipStream_t st) {
     if constexpr (hop_shape(P) == 1) {
         hop1_kernel<P, LK, DAG, HASY, NORM, NTM, HALO><<<grid, 64, 0, st>>>(a);
@@ -352,13 +421,13 @@ static void launch_halo(const HopArgs &a, dim3 grid, hipStream_t st) {
         }
         hop8_kernel<P, LK, DAG, HASY, NORM, NTM, false, HALO><<<grid, 512, 0, st>>>(a);
     } else {
-        hop4_kernel<P, LK, DAG, HASY, NORM, NTM, HALO><<<grid, 256, LQCD_HOP_EXTRA_LDS, st>>>(a);
+        hop4_kernel<P, LK, DAG, HASY, NORM, NTM, HALO><<<grid, 256, a.lds_extra, st>>>(a);
     }
 }
 
 // Boundary-slice launches (faces given) have no norm partial; the face
 // variants exist only for the other combinations.
-template <int P, int LK, bool DAG, bool HASY, bool NORM, int NTM>
+template <int P, int LK, bool DAG, bool HASY, int NORM, int NTM>
 static void launch_nt(const HopArgs &a, dim3 grid, hipStream_t st) {
     if constexpr (!NORM) {
         if (a.face[0] != nullptr) {
@@ -372,7 +441,7 @@ static void launch_nt(const HopArgs &a, dim3 grid, hipStream_t st) {
 // The cache hints are template arguments: a run-time choice between two
 // otherwise identical load or store sequences gets merged by the compiler,
 // which then drops the hint.
-template <int P, int LK, bool DAG, bool HASY, bool NORM>
+template <int P, int LK, bool DAG, bool HASY, int NORM>
 static void launch_shape(const HopArgs &a, dim3 grid, hipStream_t st) {
     switch (a.stream) {
         case 0: launch_nt<P, LK, DAG, HASY, NORM, 0>(a, grid, st); break;
@@ -382,19 +451,26 @@ static void launch_shape(const HopArgs &a, dim3 grid, hipStream_t st) {
     }
 }
 
+// norm: 0 none, 1 |out|^2 block partials, 2 CG update (needs the y term; the
+// solver applies it on the adjoint hop only)
 template <int P, int LK, bool DAG>
-static void launch_p(const HopArgs &a, bool hasy, bool norm, dim3 grid, hipStream_t st) {
+static void launch_p(const HopArgs &a, bool hasy, int norm, dim3 grid, hipStream_t st) {
     if (hasy) {
-        if (norm) launch_shape<P, LK, DAG, true, true>(a, grid, st);
-        else launch_shape<P, LK, DAG, true, false>(a, grid, st);
+        if (norm == 1) launch_shape<P, LK, DAG, true, 1>(a, grid, st);
+        else if constexpr (DAG) {
+            if (norm == 2) launch_shape<P, LK, DAG, true, 2>(a, grid, st);
+            else launch_shape<P, LK, DAG, true, 0>(a, grid, st);
+        } else {
+            launch_shape<P, LK, DAG, true, 0>(a, grid, st);
+        }
     } else {
-        if (norm) launch_shape<P, LK, DAG, false, true>(a, grid, st);
-        else launch_shape<P, LK, DAG, false, false>(a, grid, st);
+        if (norm == 1) launch_shape<P, LK, DAG, false, 1>(a, grid, st);
+        else launch_shape<P, LK, DAG, false, 0>(a, grid, st);
     }
 }
 
 template <int P, int LK>
-static void launch_l(const HopArgs &a, bool dag, bool hasy, bool norm, dim3 grid, hipStream_t st) {
+static void launch_l(const HopArgs &a, bool dag, bool hasy, int norm, dim3 grid, hipStream_t st) {
     if (dag) launch_p<P, LK, true>(a, hasy, norm, grid, st);
     else launch_p<P, LK, false>(a, hasy, norm, grid, st);
 }
@@ -422,7 +498,7 @@ int hop_launch(const HopArgs &a0, int prec, int link, bool dag, int nparity, hip
     // 16^4 and smaller); from 24^4 up the single-wave rebuild is 0.5-2.5
     // points faster
     a.rows = LQCD_HOP_ROWS && a.g.vh < ((int64_t)1 << 17) && a.y[0] == nullptr &&
-             a.y[1] == nullptr && a.partial == nullptr;
+             a.y[1] == nullptr && a.partial == nullptr && a.cg_x == nullptr;
     const int64_t spinors = (int64_t)(nparity * half_spinor_bytes(a.g, prec));
     const int64_t links = (int64_t)gauge_bytes(a.g, prec, link);
     const bool out_nt = OUT_NT;
@@ -430,10 +506,15 @@ int hop_launch(const HopArgs &a0, int prec, int link, bool dag, int nparity, hip
     // backward from the paired tile), so it keeps them cached
     const bool link_nt = LQCD_LINK_NT && !a.paired && spinors + links > INFINITY_CACHE_BYTES;
     a.stream = LQCD_HOP_STREAM >= 0 ? LQCD_HOP_STREAM : (out_nt ? 1 : 0) | (link_nt ? 2 : 0);
+    a.lds_extra = LQCD_HOP_EXTRA_LDS >= 0 ? (uint32_t)LQCD_HOP_EXTRA_LDS
+                  : prec == LQCD_F64 && a.g.vh >= ((int64_t)1 << LQCD_HOP_F64_LDS_MIN_LOG2)
+                      ? (uint32_t)LQCD_HOP_F64_LDS_EXTRA
+                      : 0u;
     dim3 grid((unsigned)(a.bpp * nparity));
     a.nblk = grid.x;
     const bool hasy = a.y[0] != nullptr || a.y[1] != nullptr;
-    const bool norm = a.partial != nullptr;
+    const int norm = a.cg_x != nullptr ? 2 : a.partial != nullptr ? 1 : 0;
+    if (norm == 2 && (!hasy || !dag || !a.partial || !a.cg_p || !a.cg_alpha)) return LQCD_EINVAL;
     if (prec == LQCD_F64) {
         if (link == 18) launch_l<LQCD_F64, 18>(a, dag, hasy, norm, grid, st);
         else launch_l<LQCD_F64, 12>(a, dag, hasy, norm, grid, st);

@@ -58,6 +58,11 @@ constexpr int64_t BRICK_L2_BUDGET = (int64_t)LQCD_BRICK_BUDGET_KB << 10;
 #ifndef LQCD_BRICK_MIN_LOG2
 #define LQCD_BRICK_MIN_LOG2 17
 #endif
+// number of z-bricks rule 1 aims for with FP64 fields (ablation switch; 8
+// gives every XCD one slab, 16 two thinner ones walked one after the other)
+#ifndef LQCD_BRICK_NB_F64
+#define LQCD_BRICK_NB_F64 8
+#endif
 // precisions that use the brick order: bit p set for precision p (F64, F32,
 // F16)
 #ifndef LQCD_BRICK_PRECS
@@ -110,6 +115,16 @@ struct HopArgs {
     // face[0] (projected half-spinors of the forward neighbours) and face[1]
     // (U^dag times the projected backward neighbours) instead of `in`
     const char *face[2];
+    // CG-update launches (cg_x set): the result A p is not stored; the
+    // epilogue does x += alpha p, r -= alpha A p on out = r and writes the
+    // block partial of |r|^2, alpha read from the device (read late: the
+    // sixth line of the arguments)
+    char *cg_x;
+    const char *cg_p;
+    const double *cg_alpha;
+    // host side: dynamic LDS bytes added to each 4-way block (limits the
+    // blocks in flight per CU; not read by the kernels)
+    uint32_t lds_extra;
 };
 
 // Tile visited by logical block b (within one parity).  With bricks of bz
@@ -156,7 +171,8 @@ inline BrickPlan brick_plan(const Geom &g, int prec) {
     const int lz = g.L[2] / gz;
     const int64_t pt = plane * gz / TILE;
     if (LQCD_BRICK_MODE == 1) {
-        for (int nb : {8, 4}) {
+        const int nb0 = prec == LQCD_F64 ? LQCD_BRICK_NB_F64 : 8;
+        for (int nb : {nb0, nb0 / 2}) {
             if (lz % nb == 0 && lz / nb >= 2) {
                 k = {(int)pt, lz / nb, lz};
                 return k;

@@ -221,9 +221,11 @@ def test_pseudofermion_force_pipeline_small():
 def test_solve_and_force_48x3x96():
     """The 48^3x96 solve-plus-force workload: FP32 12-real smoothed links
     (kappa 0.1245), mixed CG to 1e-10, recomputed X_o, Y_e, Y_o, FP32 force.
-    The residual is recomputed in FP64 through the operator entry points and
-    the force is checked against the oracle's link formula at 128 sampled
-    links (FP64 arithmetic on the same stored X, Y and links)."""
+    The residual is recomputed in FP64 through the operator entry points,
+    the recomputed X_o, Y_e, Y_o are checked stage by stage against the
+    oracle's hop of the previous stage, and the force against the oracle's
+    link formula at 128 sampled links (FP64 arithmetic on the same stored
+    X, Y and links)."""
     from tests.gpu_helpers import DeviceGather
     dims = (48, 48, 48, 96)
     kappa = 0.1245
@@ -248,6 +250,26 @@ def test_solve_and_force_48x3x96():
     Yc = P.unpack_spinor(Y)
     Uc = P.unpack_gauge(U_lo)  # the links the kernels see (row 2 rebuilt)
     Fc = P.unpack_gauge(F, dtype=torch.complex64)
+    # the recomputed fields stage by stage, each against the oracle's hop of
+    # the previous GPU stage at 256 sampled sites of its parity (and corners):
+    # X_o = D_oe X_e, Y_e = X_e - kappa^2 D_eo X_o, Y_o = (D_eo)^dag Y_e
+    rs = np.random.default_rng(18)
+    corners = np.array([[x, y, z, t] for x in (0, dims[0] - 1) for y in (0, dims[1] - 1)
+                        for z in (0, dims[2] - 1) for t in (0, dims[3] - 1)])
+    cand = np.concatenate([corners, np.stack([rs.integers(0, d, 1024) for d in dims], 1)])
+    odd_s = cand[cand.sum(1) % 2 == 1][:256]
+    even_s = cand[cand.sum(1) % 2 == 0][:256]
+    gx, gy, gu = DeviceGather(Xc), DeviceGather(Yc), DeviceGather(Uc)
+
+    def at(field, st):
+        return field[st[:, 3], st[:, 2], st[:, 1], st[:, 0]].cpu().numpy().astype(np.complex128)
+
+    for name, got, want in (
+            ("X_o", at(Xc, odd_s), dirac.dhop_at(gx, gu, odd_s)),
+            ("Y_e", at(Yc, even_s), at(Xc, even_s) - kappa ** 2 * dirac.dhop_at(gx, gu, even_s)),
+            ("Y_o", at(Yc, odd_s), dirac.dhop_at(gy, gu, odd_s, dagger=True))):
+        assert rel(got, want) < 2e-6, name
+        assert site_rel(got, want) < 2e-6, name
     rng = np.random.default_rng(12)
     links = np.stack([rng.integers(0, d, 128) for d in dims] + [rng.integers(0, 4, 128)], 1)
     links[0] = [0, 0, 0, dims[3] - 1, 3]
@@ -258,6 +280,7 @@ def test_solve_and_force_48x3x96():
     want = force.su3_force_at(G, ul)
     got = Fc[idx].cpu().numpy().astype(np.complex128)
     assert rel(got, want) < 2e-6
+    assert site_rel(got, want, per=9) < 2e-6
 
 
 # Large lattices reach the force kernel's traversal orders: 32^4 (z-slab
