@@ -277,9 +277,9 @@ size_t lqcd_cg_workspace_bytes(const lqcd_geom_t *g, int inner_prec, int inner_l
  *   search direction; it is taken every `reliable_every` iterations (0 =
  *   never on a schedule), whenever the inner residual has fallen since the
  *   last update by 1000x (FP32 inner) or 10x (F16 inner), beyond which the
- *   inner recurrence is not trusted (put off, by at most a further 100x
- *   fall, while the decay so far puts the tolerance within ten iterations,
- *   when the final update comes first),
+ *   inner recurrence is not trusted (for FP32 inner iterations put off, by
+ *   at most a further 100x fall, while the decay so far puts the tolerance
+ *   within ten iterations, when the final update comes first),
  *   and when the inner residual reaches tol (tol/2 for FP32 and F16 inner
  *   iterations, whose recurrence residual runs ahead of the true one).  The
  *   solve stops when ||b - A x|| / ||b|| <= tol in FP64.  The host reads the

@@ -218,7 +218,9 @@ static int read_gap(int left) {
 // the most that reads every ten iterations let it drift) below the drift
 // threshold: without that bound an 8^4 FP32-inner solve to 1e-12, whose
 // recurrence keeps predicting the end, took 300 iterations instead of
-// under 200.
+// under 200.  binary16 inner solves, whose drift rule fires at every
+// tenfold fall, take every drift update (put off, the 32^4 solve needed 55
+// iterations instead of 46).
 constexpr int DRIFT_DEFER = CHECK_EVERY;
 constexpr double DRIFT_HARD = 1e-4;
 
@@ -371,6 +373,7 @@ struct Solver {
         const double delta = P == LQCD_F64 ? 0.0 : P == LQCD_F32 ? DELTA_F32 : DELTA_F16;
         const double drift = delta * delta;
         const double target_inner = P == LQCD_F64 ? target : INNER_MARGIN2 * target;
+        const int defer = P == LQCD_F32 ? DRIFT_DEFER : 0;
         // residual at the last host read, the decay of log(rr) per iteration
         // between the last two reads (kept across reliable updates), and the
         // iteration of the next read
@@ -397,7 +400,7 @@ struct Solver {
                     rate = std::log(rr_it / rr_seen) / (double)(k - k_seen);
                 const int left = iterations_left(rr_it, rate, target_inner);
                 if (rr_it <= target_inner) reliable = true;
-                if (rr_it < drift * rr_ref && (left > DRIFT_DEFER || rr_it < DRIFT_HARD * drift * rr_ref))
+                if (rr_it < drift * rr_ref && (left > defer || rr_it < DRIFT_HARD * drift * rr_ref))
                     reliable = true;
                 next_read = k + read_gap(left);
                 rr_seen = rr_it;
