@@ -134,6 +134,37 @@ def dhop(psi: np.ndarray, U: np.ndarray, bc=DEFAULT_BC, dagger: bool = False) ->
     return out
 
 
+def dhop_binary16(q: np.ndarray, s: np.ndarray, U: np.ndarray, bc=DEFAULT_BC,
+                  dagger: bool = False) -> np.ndarray:
+    """D_hop (or D_hop^dag) of a spinor field held in per-site scaled binary16
+    storage: stored values q, site scales s (links.f16_spinor_parts).
+
+    Reading for binary16 storage (the paper does not treat reduced
+    precision): every hop first forms the projected spinor (1 -+ g_mu) q of
+    the neighbour site from its stored values, rounds it to binary16 (one
+    rounding of the exact sum, ties to even; rows 2 and 3 of a projected
+    spinor are unit multiples of rows 0 and 1, so rounding all four rows is
+    rounding the half-spinor), multiplies by that site's scale and by the
+    link; everything else is exact.  With no rounding this is dhop(q s).
+    """
+    from oracle.links import round_half
+
+    dims = dims_of(q)
+    out = np.zeros_like(q)
+    sg = -1.0 if dagger else 1.0
+    sc = s[..., None, None]
+    for mu in range(4):
+        p_fwd = ONE4 - sg * GAMMA[mu]
+        p_bwd = ONE4 + sg * GAMMA[mu]
+        umu = U[..., mu, :, :]
+        hf = round_half(spin_mul(p_fwd, q)) * sc
+        hb = round_half(spin_mul(p_bwd, q)) * sc
+        fwd = colour_mul(umu, shift(hf, mu, +1)) * sign_fwd(dims, bc, mu)[..., None, None]
+        bwd = shift(colour_mul(dagger3(umu), hb), mu, -1) * sign_bwd(dims, bc, mu)[..., None, None]
+        out += fwd + bwd
+    return out
+
+
 def wilson(psi, U, kappa, bc=DEFAULT_BC, dagger=False):
     """M psi = psi - kappa D_hop psi (M^dag with dagger=True).
 
@@ -180,6 +211,24 @@ def moe(psi_e, U, bc=DEFAULT_BC, dagger=False):
     is the textbook definition in the conventions of this module's header.
     """
     return project(dhop(project(psi_e, 0), U, bc, dagger), 1)
+
+
+def meo_binary16(q_o, s_o, U, bc=DEFAULT_BC, dagger=False):
+    """D_eo on binary16 storage (dhop_binary16; q_o, s_o of the odd sites).
+
+    Reading for binary16 storage; the paper does not treat reduced precision.
+    """
+    m = odd_mask(dims_of(q_o))
+    return project(dhop_binary16(q_o * m[..., None, None], s_o * m, U, bc, dagger), 0)
+
+
+def moe_binary16(q_e, s_e, U, bc=DEFAULT_BC, dagger=False):
+    """D_oe on binary16 storage (dhop_binary16; q_e, s_e of the even sites).
+
+    Reading for binary16 storage; the paper does not treat reduced precision.
+    """
+    m = ~odd_mask(dims_of(q_e))
+    return project(dhop_binary16(q_e * m[..., None, None], s_e * m, U, bc, dagger), 1)
 
 
 def mhat(x_e, U, kappa, bc=DEFAULT_BC):
@@ -247,6 +296,39 @@ def dhop_at(psi, U, sites: np.ndarray, bc=DEFAULT_BC, dagger=False) -> np.ndarra
         bwd = np.einsum("nab,nsb->nsa", dagger3(u_dn), at(psi, dn)) * s_dn[:, None, None]
         out += np.einsum("st,ntc->nsc", ONE4 - sg * GAMMA[mu], fwd)
         out += np.einsum("st,ntc->nsc", ONE4 + sg * GAMMA[mu], bwd)
+    return out
+
+
+def dhop_at_binary16(q, s, U, sites: np.ndarray, bc=DEFAULT_BC, dagger=False) -> np.ndarray:
+    """dhop_binary16 at a list of sites (rows x, y, z, t); q, s and U are
+    indexed like arrays (they may gather from larger fields on demand).
+
+    Reading for binary16 storage; the paper does not treat reduced precision.
+    """
+    from oracle.links import round_half
+
+    dims = tuple(q.shape[3 - mu] for mu in range(4))
+    sites = np.asarray(sites, dtype=np.int64)
+    out = np.zeros((sites.shape[0], 4, 3), dtype=np.complex128)
+    sg = -1.0 if dagger else 1.0
+
+    def at(field, c):
+        return field[c[:, 3], c[:, 2], c[:, 1], c[:, 0]]
+
+    for mu in range(4):
+        L = dims[mu]
+        up = sites.copy()
+        up[:, mu] = (sites[:, mu] + 1) % L
+        dn = sites.copy()
+        dn[:, mu] = (sites[:, mu] - 1) % L
+        s_up = np.where(sites[:, mu] == L - 1, float(bc[mu]), 1.0)
+        s_dn = np.where(sites[:, mu] == 0, float(bc[mu]), 1.0)
+        hf = round_half(np.einsum("st,ntc->nsc", ONE4 - sg * GAMMA[mu], at(q, up))) \
+            * at(s, up)[:, None, None]
+        hb = round_half(np.einsum("st,ntc->nsc", ONE4 + sg * GAMMA[mu], at(q, dn))) \
+            * at(s, dn)[:, None, None]
+        out += np.einsum("nab,nsb->nsa", at(U, sites)[:, mu], hf) * s_up[:, None, None]
+        out += np.einsum("nab,nsb->nsa", dagger3(at(U, dn)[:, mu]), hb) * s_dn[:, None, None]
     return out
 
 

@@ -80,6 +80,35 @@ def round_f16_spinor(psi: np.ndarray) -> np.ndarray:
     return qre.astype(np.float64) + 1j * qim.astype(np.float64)
 
 
+def f16_spinor_parts(psi: np.ndarray):
+    """The two parts of the per-site scaled binary16 storage of a spinor
+    field: the stored binary16 values q (as complex128) and the FP32 site
+    scale s (float64 array over the sites), by the rule of round_f16_spinor.
+    The arithmetic of a binary16 hop starts from q and applies s last.
+
+    Storage rounding of the reduced-precision variants; the paper does not
+    treat reduced precision.
+    """
+    re = psi.real.astype(np.float32)
+    im = psi.imag.astype(np.float32)
+    scale = np.maximum(np.abs(re).max(axis=(-1, -2)), np.abs(im).max(axis=(-1, -2)))
+    safe = np.where(scale > 0, scale, np.float32(1.0))
+    r = (np.float32(1.0) / safe).astype(np.float32)[..., None, None]
+    qre = (re * r).astype(np.float16).astype(np.float64)
+    qim = (im * r).astype(np.float16).astype(np.float64)
+    return qre + 1j * qim, safe.astype(np.float64)
+
+
+def round_half(z: np.ndarray) -> np.ndarray:
+    """Each real and imaginary part rounded to the nearest IEEE binary16
+    value (ties to even), as complex128.
+
+    Rounding of the reduced-precision variants; the paper does not treat
+    reduced precision.
+    """
+    return z.real.astype(np.float16).astype(np.float64) + 1j * z.imag.astype(np.float16).astype(np.float64)
+
+
 def su3_product(U: np.ndarray, V: np.ndarray, adj_u: bool = False, adj_v: bool = False) -> np.ndarray:
     """W = op(U) op(V) link by link (op = identity or hermitian conjugate).
 

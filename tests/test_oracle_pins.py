@@ -573,6 +573,91 @@ def test_fp16_spinor_storage_rule():
     assert got != float(np.float32(np.float32(div) * s))
 
 
+def test_fp16_spinor_parts_agree_with_storage():
+    """The (q, s) parts are the stored binary16 values and the site scale of
+    the storage rule pinned above: q are binary16 numbers, the site's
+    largest |q| is exactly 1, and fl32(q s) is round_f16_spinor."""
+    rng = np.random.default_rng(63)
+    psi = LI.gaussian_spinor(rng, (2, 2, 2, 4)) * 7.0
+    q, sc = links.f16_spinor_parts(psi)
+    assert np.array_equal(q.real, q.real.astype(np.float16).astype(np.float64))
+    assert np.array_equal(q.imag, q.imag.astype(np.float16).astype(np.float64))
+    big = np.maximum(np.abs(q.real).max(axis=(-1, -2)), np.abs(q.imag).max(axis=(-1, -2)))
+    assert np.all(big == 1.0)
+    back = (q.real * sc[..., None, None]).astype(np.float32) \
+        + 1j * (q.imag * sc[..., None, None]).astype(np.float32)
+    assert np.array_equal(back, links.round_f16_spinor(psi))
+
+
+def test_binary16_hop_exact_when_projections_are_representable():
+    """With stored values on a coarse grid every projected sum q_a + k q_b is
+    a binary16 number, so the rounding of the binary16 hop does nothing and
+    it must equal the FP64 hop of q s (a dropped scale, sign or link, or a
+    projector applied to the wrong rows, would not)."""
+    rng = np.random.default_rng(64)
+    dims = (2, 2, 4, 4)
+    U, _ = LI.workload_fields(3, dims)
+    q = (rng.integers(-8, 9, LI.spinor_shape(dims)) + 1j * rng.integers(-8, 9, LI.spinor_shape(dims))) / 16.0
+    sc = rng.uniform(0.5, 4.0, dims[::-1]).astype(np.float32).astype(np.float64)
+    for dag in (False, True):
+        want = dirac.dhop(q * sc[..., None, None], U, dagger=dag)
+        got = dirac.dhop_binary16(q, sc, U, dagger=dag)
+        assert np.max(np.abs(got - want)) <= 1e-14 * np.max(np.abs(want))
+
+
+def test_binary16_hop_rounds_the_projected_half_spinor():
+    """Constructed values fix where the binary16 hop rounds: the projected
+    sum 1 + 2^-11 is a tie between binary16 neighbours and goes to 1 (ties to
+    even); the scale multiplies the rounded value (rounding q s instead gives
+    another number at scale 3); the rounding comes before the link (with a
+    link phase, rounding the product instead differs); the sum 1 - 2^-11 is a
+    binary16 number and stays."""
+    dims = (2, 2, 2, 4)
+    t0 = 1
+    q = np.zeros(LI.spinor_shape(dims), dtype=np.complex128)
+    # site y = (0, 0, 0, t0): spin 0 = 1, spin 2 = -2^-11 (colour 0)
+    q[t0, 0, 0, 0, 0, 0] = 1.0
+    q[t0, 0, 0, 0, 2, 0] = -2.0 ** -11
+    sc = np.ones(dims[::-1])
+    sc[t0, 0, 0, 0] = 3.0
+    U = np.zeros(LI.links_shape(dims), dtype=np.complex128)
+    U[...] = np.eye(3)
+    theta = 0.3
+    phase = np.diag([np.exp(1j * theta), np.exp(-1j * theta), 1.0])
+    U[t0 - 1, 0, 0, 0, 3] = phase          # U_t(x), x = y - t
+    out = dirac.dhop_binary16(q, sc, U)
+    # forward t-hop into x = y - t: (1 - g_t) rows 0 and 2 of y, times U_t(x)
+    x0 = out[t0 - 1, 0, 0, 0]
+    assert x0[0, 0] == 3.0 * np.exp(1j * theta)     # 3 x binary16(1 + 2^-11) = 3
+    assert x0[2, 0] == -3.0 * np.exp(1j * theta)
+    exact = dirac.dhop(q * sc[..., None, None], U)[t0 - 1, 0, 0, 0]
+    assert exact[0, 0] != x0[0, 0]
+    # backward t-hop into y + t: (1 + g_t) row 0 = 1 - 2^-11, representable
+    x1 = out[t0 + 1, 0, 0, 0]
+    assert x1[0, 0] == 3.0 * (1.0 - 2.0 ** -11)
+    # rounding q s (scale first) would give binary16(3 (1 + 2^-11)) = 3 + 2^-9
+    assert float(np.float16(3.0 * (1 + 2.0 ** -11))) != 3.0
+    # rounding after the link: binary16 of the phase times 1 + 2^-11
+    after = complex(np.float16((np.exp(1j * theta) * (1 + 2.0 ** -11)).real),
+                    np.float16((np.exp(1j * theta) * (1 + 2.0 ** -11)).imag)) * 3.0
+    assert after != x0[0, 0]
+
+
+def test_binary16_sites_match_field():
+    """The site-by-site binary16 hop equals the field version."""
+    rng = np.random.default_rng(65)
+    dims = (4, 2, 2, 4)
+    U, psi = LI.workload_fields(4, dims)
+    q, sc = links.f16_spinor_parts(psi)
+    Ur = links.reconstruct(links.round_f16_links(links.compress(U)))
+    sites = np.stack([rng.integers(0, d, 40) for d in dims], 1)
+    for dag in (False, True):
+        field = dirac.dhop_binary16(q, sc, Ur, dagger=dag)
+        got = dirac.dhop_at_binary16(q, sc, Ur, sites, dagger=dag)
+        want = field[sites[:, 3], sites[:, 2], sites[:, 1], sites[:, 0]]
+        assert np.max(np.abs(got - want)) <= 1e-14 * np.max(np.abs(want))
+
+
 # ----------------------------------------------------------------------------
 # generators
 # ----------------------------------------------------------------------------
