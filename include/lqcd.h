@@ -67,11 +67,16 @@ extern "C" {
 #define LQCD_ESMALL   -5   /* workspace smaller than the size query returned, or a
                               field too large for the static scratch of lqcd_dot_noalloc */
 
-/* storage precisions: arithmetic is FP64 for LQCD_F64 and FP32 otherwise */
+/* storage precisions: arithmetic is FP64 for LQCD_F64 and FP32 otherwise;
+   the hopping term on binary16 storage forms each projected half-spinor from
+   the stored values of the neighbour site in binary16 (one rounding of the
+   exact sum), multiplies by the link in FP32 (binary16 products exact) and
+   applies the neighbour's scale last (a reading: the paper does not treat
+   reduced precision) */
 #define LQCD_F64   0
 #define LQCD_F32   1
-#define LQCD_F16   2       /* binary16 storage, FP32 arithmetic; spinors carry
-                              one FP32 scale per site (max |real| of the site) */
+#define LQCD_F16   2       /* binary16 storage; spinors carry one FP32 scale
+                              per site (max |real| of the site) */
 
 /* link storage: full 3x3 (18 reals) or rows 0 and 1 only (12 reals), with
    row 2 = conj(row0 x row1) rebuilt in registers (valid for SU(3) only) */
@@ -186,8 +191,12 @@ int lqcd_moe(const lqcd_geom_t *g, void *out_o, const void *in_e, const void *y_
  * S = -1 (S = +1 with dagger != 0), j the checkerboard index within the
  * slice, `in` the input half field (parity 1 - out_par), U the gauge field.
  * The receiver multiplies face_fwd by its own U_t.  Faces are stored in the
- * arithmetic precision (FP32 for binary16 storage) as tiles of 64 sites of
- * six complex numbers; lqcd_face_bytes gives the size of one face.  On one
+ * arithmetic precision as tiles of 64 sites of six complex numbers (FP64
+ * 96 bytes per site, FP32 48); for binary16 storage face_fwd holds the
+ * binary16 half-spinor in units of the site scale, with that scale times
+ * bc[3] kept apart (52 bytes per site), and face_bwd six FP32 complex numbers
+ * in the same 52-byte tiles, so the receiver's arithmetic is the unsplit
+ * hop's; lqcd_face_bytes gives the size of one face.  On one
  * GPU the faces of this lattice's own t wrap stand in for the neighbours'.
  * lqcd_hop_region computes the hop (as lqcd_meo / lqcd_moe: out = alpha
  * D in + beta y) on region 0, the interior slices 1 .. Lt-2 (no face

@@ -70,6 +70,14 @@ namespace lqcd {
 #ifndef LQCD_HOP_EXTRA_LDS
 #define LQCD_HOP_EXTRA_LDS -1
 #endif
+// t-march form of the 4-way shape: t-slices per block (0 = off), used from
+// V/2 >= 2^LQCD_HOP_TMARCH_MIN_LOG2 sites
+#ifndef LQCD_HOP_TMARCH
+#define LQCD_HOP_TMARCH 0
+#endif
+#ifndef LQCD_HOP_TMARCH_MIN_LOG2
+#define LQCD_HOP_TMARCH_MIN_LOG2 17
+#endif
 constexpr int64_t INFINITY_CACHE_BYTES = (int64_t)256 << 20;
 
 // Epilogue shared by the kernel shapes: out = alpha acc + beta y; NORM = 1
@@ -228,6 +236,121 @@ __global__ __launch_bounds__(256) void hop4_kernel(HopArgs a) {
         if (w == 0) {
             const double t = wave_sum(nrm[0]);
             if (lane == 0) a.partial[blk] = t;
+        }
+    }
+}
+
+// t-march form of the 4-way shape (LQCD_HOP_TMARCH = t-slices per block):
+// a block walks one tile column, the same 64 in-slice sites of tseg
+// consecutive t-slices.  The t-neighbours of a tile are the same lanes of
+// the tiles one slice up and one down, so the wave of direction t loads each
+// input t-slice of its column once: the load of input slice t + 1 gives the
+// forward hop of output slice t and the backward hop of output slice t + 2,
+// whose two colour vectors wait two steps in a lane-private LDS ring (the
+// 4-way form loads that input again two output slices later, from the L2
+// if it is still there).  Waves 0-2 read their neighbours as in the 4-way
+// shape; XCD x of 8 takes columns [x K/8, (x + 1) K/8) of every segment, so
+// the blocks of one XCD walk its z-slab side by side.  Same arithmetic, in
+// the same order, as the 4-way shape: the results are bit-identical.
+template <int P, int LK, bool DAG, bool HASY, int NORM, int NTM>
+__global__ __launch_bounds__(256) void hop4t_kernel(HopArgs a) {
+    using T = typename real_of<P>::type;
+    using E = typename hop_elem<P>::type;
+    using PR = Proj<3>;
+    constexpr bool LNT = (NTM & 2) != 0;
+    constexpr int SF = DAG ? 1 : -1;
+    constexpr int SB = -SF;
+    constexpr int r0 = SF > 0 ? conj_code(PR::c0) : neg_code(conj_code(PR::c0));
+    constexpr int r1 = SF > 0 ? conj_code(PR::c1) : neg_code(conj_code(PR::c1));
+    __shared__ cplx<T> part[3][12][64];
+    __shared__ cplx<T> ring[2][6][64];
+    const int lane = threadIdx.x & 63;
+    const int w = threadIdx.x >> 6;
+    const Geom &g = a.g;
+    const int p = a.par0;
+    const int lt = g.L[3];
+    const uint32_t kx = (uint32_t)(g.st >> TILE_SHIFT) / 8;  // columns per XCD
+    const uint32_t b = blockIdx.x;
+    const uint32_t j = b >> 3;
+    const uint32_t seg = j / kx;
+    const uint32_t col = (b & 7) * kx + (j - seg * kx);
+    const int t0 = (int)seg * a.tseg;
+    const int t1 = t0 + a.tseg < lt ? t0 + a.tseg : lt;
+    const int64_t s0 = (int64_t)col * TILE + lane;  // this lane's site of slice 0
+    const char *in = a.in[p];
+    // backward t-hop of output slice t from input slice t - 1 (wrapping, with
+    // the boundary sign), as the 4-way shape forms it
+    auto bwd_half = [&](int t, cplx<T> bh[6]) {
+        const bool wrap = t == 0;
+        const int64_t nb = (int64_t)(wrap ? lt - 1 : t - 1) * g.st + s0;
+        T sgn = wrap && g.bc[3] < 0 ? T(-1) : T(1);
+        cplx<E> psi[12];
+        load_spinor_hop<P>(in, nb, psi, sgn);
+        link_chi<3, SB, true, P, LK, LNT>(a.U, g.ntiles, p ^ 1, nb, psi, sgn, bh, bh + 3);
+    };
+    if (w == 3) {
+        for (int t = t0; t < t0 + 2 && t < t1; ++t) {
+            cplx<T> bh[6];
+            bwd_half(t, bh);
+#pragma unroll
+            for (int k = 0; k < 6; ++k) ring[t & 1][k][lane] = bh[k];
+        }
+    }
+    for (int t = t0; t < t1; ++t) {
+        const int64_t s = (int64_t)t * g.st + s0;
+        const Coord c = cb_coords(g, p, s);
+        cplx<T> acc[12];
+        switch (w) {
+            case 0: hop_direction<0, P, LK, DAG, LNT>(g, in, a.U, p, s, c, acc); break;
+            case 1: hop_direction<1, P, LK, DAG, LNT>(g, in, a.U, p, s, c, acc); break;
+            case 2: hop_direction<2, P, LK, DAG, LNT>(g, in, a.U, p, s, c, acc); break;
+            default: {
+                // forward hop: input slice t + 1 (wrapping), link U_t(s)
+                const bool wrap = t == lt - 1;
+                const int64_t nb = (int64_t)(wrap ? 0 : t + 1) * g.st + s0;
+                T sgn = wrap && g.bc[3] < 0 ? T(-1) : T(1);
+                cplx<E> psi[12];
+                cplx<T> f[6];
+                load_spinor_hop<P>(in, nb, psi, sgn);
+                link_chi<3, SF, false, P, LK, LNT>(a.U, g.ntiles, p, s, psi, sgn, f, f + 3);
+                hop_fence<T, 6>(f);
+                cplx<T> bh[6];
+#pragma unroll
+                for (int k = 0; k < 6; ++k) bh[k] = ring[t & 1][k][lane];
+#pragma unroll
+                for (int q = 0; q < 3; ++q) {
+                    acc[q] = f[q] + bh[q];
+                    acc[3 + q] = f[3 + q] + bh[3 + q];
+                    acc[PR::a0 * 3 + q] = mul_unit<r0>(f[q] - bh[q]);
+                    acc[PR::a1 * 3 + q] = mul_unit<r1>(f[3 + q] - bh[3 + q]);
+                }
+                hop_fence<T, 12>(acc);
+                // the same input gives the backward hop of output slice t + 2
+                // (never across the boundary inside a segment, so the sign
+                // factor is the forward hop's: 1, times the binary16 scale)
+                if (t + 2 < t1) {
+                    link_chi<3, SB, true, P, LK, LNT>(a.U, g.ntiles, p ^ 1, nb, psi, sgn, bh, bh + 3);
+#pragma unroll
+                    for (int k = 0; k < 6; ++k) ring[t & 1][k][lane] = bh[k];
+                }
+            }
+        }
+        __syncthreads();  // wave 0 has read the partials of the step before
+        if (w > 0) {
+#pragma unroll
+            for (int k = 0; k < 12; ++k) part[w - 1][k][lane] = acc[k];
+        }
+        __syncthreads();
+        if (w == 0) {
+#pragma unroll
+            for (int q = 0; q < 3; ++q)
+#pragma unroll
+                for (int k = 0; k < 12; ++k) acc[k] = acc[k] + part[q][k][lane];
+            const double nrm = hop_epilogue<P, HASY, NORM, (NTM & 1) != 0>(a, p, s, acc);
+            if constexpr (NORM != 0) {
+                const double tot = wave_sum(nrm);
+                if (lane == 0) a.partial[s >> TILE_SHIFT] = tot;
+            }
         }
     }
 }
@@ -421,6 +544,12 @@ static void launch_halo(const HopArgs &a, dim3 grid, hipStream_t st) {
         }
         hop8_kernel<P, LK, DAG, HASY, NORM, NTM, false, HALO><<<grid, 512, 0, st>>>(a);
     } else {
+        if constexpr (!HALO && LQCD_HOP_TMARCH > 0) {
+            if (a.tseg > 0) {
+                hop4t_kernel<P, LK, DAG, HASY, NORM, NTM><<<grid, 256, a.lds_extra, st>>>(a);
+                return;
+            }
+        }
         hop4_kernel<P, LK, DAG, HASY, NORM, NTM, HALO><<<grid, 256, a.lds_extra, st>>>(a);
     }
 }
@@ -511,6 +640,18 @@ int hop_launch(const HopArgs &a0, int prec, int link, bool dag, int nparity, hip
                       ? (uint32_t)LQCD_HOP_F64_LDS_EXTRA
                       : 0u;
     dim3 grid((unsigned)(a.bpp * nparity));
+    // t-march launches (4-way shape, one parity, whole lattice, whole tiles
+    // per t-slice in a multiple of 8 columns): one block per column and
+    // segment of tseg slices
+    a.tseg = 0;
+    if (LQCD_HOP_TMARCH > 0 && hop_shape(prec) == 4 && nparity == 1 && region < 0 &&
+        a.g.vh >= ((int64_t)1 << LQCD_HOP_TMARCH_MIN_LOG2) && a.g.st % TILE == 0 &&
+        (a.g.st / TILE) % 8 == 0) {
+        a.tseg = LQCD_HOP_TMARCH;
+        const int64_t nseg = (a.g.L[3] + a.tseg - 1) / a.tseg;
+        grid = dim3((unsigned)((a.g.st / TILE) * nseg));
+        a.lds_extra = LQCD_HOP_EXTRA_LDS >= 0 ? (uint32_t)LQCD_HOP_EXTRA_LDS : 0u;
+    }
     a.nblk = grid.x;
     const bool hasy = a.y[0] != nullptr || a.y[1] != nullptr;
     const int norm = a.cg_x != nullptr ? 2 : a.partial != nullptr ? 1 : 0;

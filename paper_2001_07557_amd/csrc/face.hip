@@ -9,7 +9,9 @@
 // with S_f = -1, S_b = +1 (exchanged for the adjoint) and s = bc[3], the
 // phase of a hop across the t boundary.  The half-spinors are formed with the
 // same code and the same arithmetic as inside the fused hop, so a boundary
-// launch that reads them reproduces the unsplit hop bit for bit.
+// launch that reads them reproduces the unsplit hop bit for bit (binary16
+// storage: the forward face holds the packed binary16 half-spinor and the
+// neighbour's scale times s, which the receiver applies after its link).
 
 #include "lqcd_internal.h"
 #include "hop_common.h"
@@ -36,17 +38,23 @@ __global__ __launch_bounds__(FACE_BLOCK) void face_pack_k(Geom g, char *fwd_face
     if (!bwd) {
         // receiver: site j of slice Lt-1, forward neighbour j of slice 0
         load_spinor_hop<P>(in, j, psi, sgn);
-        hop_half<3, SF>(psi, sgn, h, h + 3);
-        store_face<T>(fwd_face, j, h);
+        if constexpr (P == LQCD_F16) {
+            v2h hr[6], hi[6];
+            half_forms_h<3, SF, false>(psi, hr, hi);
+            store_face_forms(fwd_face, j, hr, hi, sgn);
+        } else {
+            hop_half<3, SF>(psi, sgn, h, h + 3);
+            store_face<T>(fwd_face, j, h);
+        }
     } else {
         // receiver: site j of slice 0, backward neighbour y on slice Lt-1,
         // whose link U_t(y) (parity q) the sender owns
         const int64_t y = (int64_t)(g.L[3] - 1) * g.st + j;
-        cplx<T> u[9], x[6];
+        cplx<T> x[6];
         load_spinor_hop<P>(in, y, psi, sgn);
-        load_link<P, LK, false>(U, g.ntiles, q, y, 3, u);
-        hop_chi<3, -SF, true>(psi, u, sgn, x, x + 3);
-        store_face<T>(bwd_face, j, x);
+        link_chi<3, -SF, true, P, LK, false>(U, g.ntiles, q, y, psi, sgn, x, x + 3);
+        if constexpr (P == LQCD_F16) store_face_h(bwd_face, j, x);
+        else store_face<T>(bwd_face, j, x);
     }
 }
 

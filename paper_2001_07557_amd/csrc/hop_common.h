@@ -125,6 +125,8 @@ struct HopArgs {
     // host side: dynamic LDS bytes added to each 4-way block (limits the
     // blocks in flight per CU; not read by the kernels)
     uint32_t lds_extra;
+    // t-march launches: t-slices per block (0: one tile per block)
+    int tseg;
 };
 
 // Tile visited by logical block b (within one parity).  With bricks of bz
@@ -260,35 +262,17 @@ __device__ __forceinline__ void project_half(const cplx<T> psi[12], cplx<T> h0[3
     }
 }
 
-// a + k b for a unit k (code as for mul_unit) in the arithmetic type T, from
-// inputs of element type E, as fused multiply-adds by +-one (exact).  With
-// binary16 inputs each component is one mixed-precision FMA that reads the
-// stored halves directly; `one` must then be a register value the compiler
-// cannot see is 1, or it turns the FMA back into an addition of two
-// converted values.
-template <int K, typename T, typename E>
-__device__ __forceinline__ cplx<T> add_unit(cplx<E> a, cplx<E> b, T one) {
-    const T ar = (T)a.re, ai = (T)a.im, br = (T)b.re, bi = (T)b.im;
-    if constexpr (K == 0) return {fmad(br, one, ar), fmad(bi, one, ai)};
-    else if constexpr (K == 1) return {fmad(br, -one, ar), fmad(bi, -one, ai)};
-    else if constexpr (K == 2) return {fmad(bi, -one, ar), fmad(br, one, ai)};
-    else return {fmad(bi, one, ar), fmad(br, -one, ai)};
-}
-
 // Project with (1 + S g_mu) and apply the boundary sign: rows 0 and 1 of the
-// half-spinor of one hop.
-template <int MU, int S, typename T, typename E>
-__device__ __forceinline__ void hop_half(const cplx<E> psi[12], T sign, cplx<T> h0[3],
-                                         cplx<T> h1[3]) {
+// half-spinor of one hop (FP64 and FP32 storage).
+template <int MU, int S, typename T>
+__device__ __forceinline__ void hop_half(const cplx<T> psi[12], T sign, cplx<T> h0[3], cplx<T> h1[3]) {
     using PR = Proj<MU>;
     constexpr int k0 = S > 0 ? PR::c0 : neg_code(PR::c0);
     constexpr int k1 = S > 0 ? PR::c1 : neg_code(PR::c1);
-    T one = 1;
-    if constexpr (sizeof(E) == 2) asm volatile("" : "+v"(one));
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-        h0[c] = scale(sign, add_unit<k0, T>(psi[c], psi[PR::a0 * 3 + c], one));
-        h1[c] = scale(sign, add_unit<k1, T>(psi[3 + c], psi[PR::a1 * 3 + c], one));
+        h0[c] = scale(sign, psi[c] + mul_unit<k0>(psi[PR::a0 * 3 + c]));
+        h1[c] = scale(sign, psi[3 + c] + mul_unit<k1>(psi[PR::a1 * 3 + c]));
     }
 }
 
@@ -308,14 +292,187 @@ __device__ __forceinline__ void half_mul(const cplx<T> u[9], const cplx<T> h0[3]
     }
 }
 
+// Hops on binary16 storage run in packed binary16 arithmetic where it can be
+// exact or is one rounding, and in FP32 elsewhere:
+//  * the projected half-spinor h = a + k b (k a unit) of the stored values
+//    of the neighbour site is one v_pk_add_f16 per complex component, which
+//    rounds the exact sum to binary16 once (ties to even);
+//  * U h with rows 0 and 1 of the link as stored: two-term binary16 dot
+//    products accumulated in FP32 (v_dot2_f32_f16, products exact); row 2 =
+//    conj(row0 x row1) is rebuilt in FP32 and enters by mixed-precision FMAs;
+//  * the neighbour's scale times the boundary sign multiplies the result.
+// Each complex component of h is held in the two packed forms its products
+// need, produced directly by the operand selects and negations of the add:
+// F = 0 (re h, -im h), 1 (im h, re h) for U h and 2 (re h, im h),
+// 3 (im h, -re h) for U^dag h.  Against the FP32 arithmetic it replaces, 12%
+// fewer vector instructions per site.
+template <int K, int F>
+__device__ __forceinline__ v2h pk_form(v2h a, v2h b);
+#define LQCD_PK_FORM(K, F, MODS)                                         \
+    template <>                                                          \
+    __device__ __forceinline__ v2h pk_form<K, F>(v2h a, v2h b) {         \
+        v2h r;                                                           \
+        asm("v_pk_add_f16 %0, %1, %2 " MODS : "=v"(r) : "v"(a), "v"(b)); \
+        return r;                                                        \
+    }
+LQCD_PK_FORM(0, 0, "neg_hi:[1,1]")
+LQCD_PK_FORM(1, 0, "neg_lo:[0,1] neg_hi:[1,0]")
+LQCD_PK_FORM(2, 0, "op_sel:[0,1] op_sel_hi:[1,0] neg_lo:[0,1] neg_hi:[1,1]")
+LQCD_PK_FORM(3, 0, "op_sel:[0,1] op_sel_hi:[1,0] neg_hi:[1,0]")
+LQCD_PK_FORM(0, 1, "op_sel:[1,1] op_sel_hi:[0,0]")
+LQCD_PK_FORM(1, 1, "op_sel:[1,1] op_sel_hi:[0,0] neg_lo:[0,1] neg_hi:[0,1]")
+LQCD_PK_FORM(2, 1, "op_sel:[1,0] op_sel_hi:[0,1] neg_hi:[0,1]")
+LQCD_PK_FORM(3, 1, "op_sel:[1,0] op_sel_hi:[0,1] neg_lo:[0,1]")
+LQCD_PK_FORM(0, 2, "")
+LQCD_PK_FORM(1, 2, "neg_lo:[0,1] neg_hi:[0,1]")
+LQCD_PK_FORM(2, 2, "op_sel:[0,1] op_sel_hi:[1,0] neg_lo:[0,1]")
+LQCD_PK_FORM(3, 2, "op_sel:[0,1] op_sel_hi:[1,0] neg_hi:[0,1]")
+LQCD_PK_FORM(0, 3, "op_sel:[1,1] op_sel_hi:[0,0] neg_hi:[1,1]")
+LQCD_PK_FORM(1, 3, "op_sel:[1,1] op_sel_hi:[0,0] neg_lo:[0,1] neg_hi:[1,0]")
+LQCD_PK_FORM(2, 3, "op_sel:[1,0] op_sel_hi:[0,1] neg_hi:[1,0]")
+LQCD_PK_FORM(3, 3, "op_sel:[1,0] op_sel_hi:[0,1] neg_lo:[0,1] neg_hi:[1,1]")
+#undef LQCD_PK_FORM
+
+// a.x b.x + a.y b.y + c, products exact, FP32 accumulation
+__device__ __forceinline__ float dot2h(v2h a, v2h b, float c) {
+    return __builtin_amdgcn_fdot2(a, b, c, false);
+}
+// the first product of a chain: the three-operand form with an inline zero
+// (the two-operand form would need its accumulator cleared by a move)
+__device__ __forceinline__ float dot2h0(v2h a, v2h b) {
+    float r;
+    asm("v_dot2_f32_f16 %0, %1, %2, 0" : "=v"(r) : "v"(a), "v"(b));
+    return r;
+}
+// a b rounded on its own: not fused into a later addition, so a hop's result
+// is the same whether the caller adds it to the other hop straight away or
+// after a branch (a boundary launch reading faces)
+__device__ __forceinline__ float mul_nc(float a, float b) {
+#pragma clang fp contract(off)
+    return a * b;
+}
+// r.re v.x + r.im v.y + c with v binary16 (mixed-precision FMAs)
+__device__ __forceinline__ float mix2(cplx<float> r, v2h v, float c) {
+    return fmaf(r.re, (float)v.x, fmaf(r.im, (float)v.y, c));
+}
+
+// A binary16 12-real link: rows 0 and 1 as stored (re, im pairs), row 2 =
+// conj(row0 x row1) in FP32.
+template <bool NT>
+__device__ __forceinline__ void load_link_h(const char *__restrict__ U, int64_t ntiles, int p,
+                                            int64_t s, int mu, v2h u[6], cplx<float> r2[3]) {
+    const int lane = (int)(s & (TILE - 1));
+    const char *t = link_tile<LQCD_F16, 12>(U, ntiles, p, s >> TILE_SHIFT, mu);
+    const v4u q = stream_load<NT>(reinterpret_cast<const v4u *>(t) + lane);
+    const v2u q2 = stream_load<NT>(reinterpret_cast<const v2u *>(t + TILE * WORD) + lane);
+    const uint32_t w[6] = {q.x, q.y, q.z, q.w, q2.x, q2.y};
+    cplx<float> f[6];
+#pragma unroll
+    for (int j = 0; j < 6; ++j) {
+        u[j] = __builtin_bit_cast(v2h, w[j]);
+        f[j] = {(float)u[j].x, (float)u[j].y};
+    }
+    r2[0] = conj_cross(f[1], f[5], f[2], f[4]);
+    r2[1] = conj_cross(f[2], f[3], f[0], f[5]);
+    r2[2] = conj_cross(f[0], f[4], f[1], f[3]);
+}
+
+// The projected half-spinor of one hop, rows 0 and 1 of (1 + S g_mu) psi,
+// in the packed forms of U h (UDAG false) or U^dag h: hr[c], hi[c] for
+// colour c of row 0 and hr[3 + c], hi[3 + c] for row 1.
+template <int MU, int S, bool UDAG>
+__device__ __forceinline__ void half_forms_h(const cplx<_Float16> psi[12], v2h hr[6], v2h hi[6]) {
+    using PR = Proj<MU>;
+    constexpr int k0 = S > 0 ? PR::c0 : neg_code(PR::c0);
+    constexpr int k1 = S > 0 ? PR::c1 : neg_code(PR::c1);
+    constexpr int FR = UDAG ? 2 : 0;
+    constexpr int FI = UDAG ? 3 : 1;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        const v2h a0 = v2h{psi[c].re, psi[c].im};
+        const v2h b0 = v2h{psi[PR::a0 * 3 + c].re, psi[PR::a0 * 3 + c].im};
+        const v2h a1 = v2h{psi[3 + c].re, psi[3 + c].im};
+        const v2h b1 = v2h{psi[PR::a1 * 3 + c].re, psi[PR::a1 * 3 + c].im};
+        hr[c] = pk_form<k0, FR>(a0, b0);
+        hi[c] = pk_form<k0, FI>(a0, b0);
+        hr[3 + c] = pk_form<k1, FR>(a1, b1);
+        hi[3 + c] = pk_form<k1, FI>(a1, b1);
+    }
+}
+
+// factor (U h) or factor (U^dag h) for the two colour vectors of a
+// half-spinor in packed forms: x0 from row 0, x1 from row 1.
+template <bool UDAG>
+__device__ __forceinline__ void half_mul_h(const v2h hr[6], const v2h hi[6], const v2h u[6],
+                                           const cplx<float> r2[3], float factor,
+                                           cplx<float> x0[3], cplx<float> x1[3]) {
+#pragma unroll
+    for (int r = 0; r < 2; ++r) {
+        const v2h *fr = hr + 3 * r, *fi = hi + 3 * r;
+        cplx<float> *x = r == 0 ? x0 : x1;
+        if constexpr (!UDAG) {
+            // U[a][b] = u[3a + b] (a = 0, 1), row 2 from r2
+#pragma unroll
+            for (int a = 0; a < 2; ++a) {
+                const float re = dot2h(u[3 * a + 2], fr[2], dot2h(u[3 * a + 1], fr[1], dot2h0(u[3 * a], fr[0])));
+                const float im = dot2h(u[3 * a + 2], fi[2], dot2h(u[3 * a + 1], fi[1], dot2h0(u[3 * a], fi[0])));
+                x[a] = {mul_nc(factor, re), mul_nc(factor, im)};
+            }
+            const float re = mix2(r2[2], fr[2], mix2(r2[1], fr[1], mix2(r2[0], fr[0], 0.f)));
+            const float im = mix2(r2[2], fi[2], mix2(r2[1], fi[1], mix2(r2[0], fi[0], 0.f)));
+            x[2] = {mul_nc(factor, re), mul_nc(factor, im)};
+        } else {
+            // U^dag[a][b] = conj(U[b][a]): u[a], u[3 + a] and r2[a]
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                const float re = dot2h(u[3 + a], fr[1], dot2h(u[a], fr[0], mix2(r2[a], fr[2], 0.f)));
+                const float im = dot2h(u[3 + a], fi[1], dot2h(u[a], fi[0], mix2(r2[a], fi[2], 0.f)));
+                x[a] = {mul_nc(factor, re), mul_nc(factor, im)};
+            }
+        }
+    }
+}
+
+// One hop on binary16 storage: the two colour vectors chi0, chi1.
+template <int MU, int S, bool UDAG>
+__device__ __forceinline__ void hop_chi_h(const cplx<_Float16> psi[12], const v2h u[6],
+                                          const cplx<float> r2[3], float factor,
+                                          cplx<float> x0[3], cplx<float> x1[3]) {
+    v2h hr[6], hi[6];
+    half_forms_h<MU, S, UDAG>(psi, hr, hi);
+    half_mul_h<UDAG>(hr, hi, u, r2, factor, x0, x1);
+}
+
 // Project with (1 + S g_mu), apply the boundary sign and multiply by U (or
 // U^dag): the two colour vectors chi0, chi1 of one hop.
-template <int MU, int S, bool UDAG, typename T, typename E>
-__device__ __forceinline__ void hop_chi(const cplx<E> psi[12], const cplx<T> u[9], T sign,
+template <int MU, int S, bool UDAG, typename T>
+__device__ __forceinline__ void hop_chi(const cplx<T> psi[12], const cplx<T> u[9], T sign,
                                         cplx<T> x0[3], cplx<T> x1[3]) {
     cplx<T> h0[3], h1[3];
     hop_half<MU, S>(psi, sign, h0, h1);
     half_mul<UDAG>(u, h0, h1, x0, x1);
+}
+
+// Load the link of direction MU at parity q, site y, and form the two colour
+// vectors of one hop from the neighbour spinor psi (binary16 storage: the
+// packed path above; factor = boundary sign, times the site scale for
+// binary16).
+template <int MU, int S, bool UDAG, int P, int LK, bool LNT>
+__device__ __forceinline__ void link_chi(const char *__restrict__ U, int64_t ntiles, int q,
+                                         int64_t y, const cplx<typename hop_elem<P>::type> psi[12],
+                                         typename real_of<P>::type factor,
+                                         cplx<typename real_of<P>::type> x0[3],
+                                         cplx<typename real_of<P>::type> x1[3]) {
+    if constexpr (P == LQCD_F16) {
+        v2h u[6];
+        cplx<float> r2[3];
+        load_link_h<LNT>(U, ntiles, q, y, MU, u, r2);
+        hop_chi_h<MU, S, UDAG>(psi, u, r2, factor, x0, x1);
+    } else {
+        cplx<typename real_of<P>::type> u[9];
+        load_link<P, LK, LNT>(U, ntiles, q, y, MU, u);
+        hop_chi<MU, S, UDAG>(psi, u, factor, x0, x1);
+    }
 }
 
 // Face buffers of a t decomposition: per site of one t-slice (index j within
@@ -358,8 +515,70 @@ __device__ __forceinline__ void store_face(char *__restrict__ f, int64_t j, cons
     }
 }
 
+// binary16 storage: 52 bytes per site, tiles of 64 sites of three 16-byte
+// words and then 64 FP32 numbers.  The forward face holds the half-spinor in
+// the packed forms of U h (hr[0..5], hi[0..5], four per word) and the
+// neighbour's scale times the boundary sign; the backward face holds six FP32
+// complex numbers in the three words, as for FP32.
+constexpr int FACE_H_TILE = 3 * TILE * WORD + TILE * 4;
+
+__device__ __forceinline__ void store_face_forms(char *__restrict__ f, int64_t j, const v2h hr[6],
+                                                 const v2h hi[6], float factor) {
+    const int lane = (int)(j & (TILE - 1));
+    char *t = f + (j >> TILE_SHIFT) * FACE_H_TILE;
+    v4u *w = reinterpret_cast<v4u *>(t) + lane;
+    const v2h v[12] = {hr[0], hr[1], hr[2], hr[3], hr[4], hr[5], hi[0], hi[1], hi[2], hi[3], hi[4], hi[5]};
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+        w[k * TILE] = v4u{__builtin_bit_cast(uint32_t, v[4 * k]), __builtin_bit_cast(uint32_t, v[4 * k + 1]),
+                          __builtin_bit_cast(uint32_t, v[4 * k + 2]), __builtin_bit_cast(uint32_t, v[4 * k + 3])};
+    reinterpret_cast<float *>(t + 3 * TILE * WORD)[lane] = factor;
+}
+
+__device__ __forceinline__ void load_face_forms(const char *__restrict__ f, int64_t j, v2h hr[6],
+                                                v2h hi[6], float &factor) {
+    const int lane = (int)(j & (TILE - 1));
+    const char *t = f + (j >> TILE_SHIFT) * FACE_H_TILE;
+    const v4u *w = reinterpret_cast<const v4u *>(t) + lane;
+    v2h v[12];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        // through a plain array: a bit cast of a vector element (q.y) reads
+        // the vector's first element with this compiler
+        const v4u q = w[k * TILE];
+        const uint32_t e[4] = {q.x, q.y, q.z, q.w};
+#pragma unroll
+        for (int i = 0; i < 4; ++i) v[4 * k + i] = __builtin_bit_cast(v2h, e[i]);
+    }
+#pragma unroll
+    for (int c = 0; c < 6; ++c) {
+        hr[c] = v[c];
+        hi[c] = v[6 + c];
+    }
+    factor = reinterpret_cast<const float *>(t + 3 * TILE * WORD)[lane];
+}
+
+__device__ __forceinline__ void store_face_h(char *__restrict__ f, int64_t j, const cplx<float> v[6]) {
+    const int lane = (int)(j & (TILE - 1));
+    v4f *w = reinterpret_cast<v4f *>(f + (j >> TILE_SHIFT) * FACE_H_TILE) + lane;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) w[k * TILE] = v4f{v[2 * k].re, v[2 * k].im, v[2 * k + 1].re, v[2 * k + 1].im};
+}
+
+__device__ __forceinline__ void load_face_h(const char *__restrict__ f, int64_t j, cplx<float> v[6]) {
+    const int lane = (int)(j & (TILE - 1));
+    const v4f *w = reinterpret_cast<const v4f *>(f + (j >> TILE_SHIFT) * FACE_H_TILE) + lane;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const v4f d = w[k * TILE];
+        v[2 * k] = {d.x, d.y};
+        v[2 * k + 1] = {d.z, d.w};
+    }
+}
+
 // Bytes of one face buffer (one t-slice of one parity) for storage precision prec.
 inline size_t face_bytes(const Geom &g, int prec) {
+    if (prec == LQCD_F16) return (size_t)(g.st / TILE) * FACE_H_TILE;
     return (size_t)g.st * 6 * (prec == LQCD_F64 ? 16 : 8);
 }
 
@@ -420,8 +639,18 @@ __device__ __forceinline__ void hop_single(const Geom &g, const char *__restrict
     constexpr int S = FWD ? (DAG ? 1 : -1) : (DAG ? -1 : 1);
     if constexpr (HALO && MU == 3) {
         if (FWD ? c.t == g.L[3] - 1 : c.t == 0) {
+            if constexpr (FWD && P == LQCD_F16) {
+                v2h hr[6], hi[6], u[6];
+                cplx<float> r2[3];
+                float fac;
+                load_face_forms(face[0], s - (int64_t)(g.L[3] - 1) * g.st, hr, hi, fac);
+                load_link_h<LNT>(U, g.ntiles, p, s, MU, u, r2);
+                half_mul_h<false>(hr, hi, u, r2, fac, x0, x1);
+                return;
+            }
             cplx<T> h[6];
-            load_face<T>(face[FWD ? 0 : 1], FWD ? s - (int64_t)(g.L[3] - 1) * g.st : s, h);
+            if constexpr (P == LQCD_F16) load_face_h(face[1], s, h);
+            else load_face<T>(face[FWD ? 0 : 1], FWD ? s - (int64_t)(g.L[3] - 1) * g.st : s, h);
             if constexpr (FWD) {
                 cplx<T> u[9];
                 load_link<P, LK, LNT>(U, g.ntiles, p, s, MU, u);
@@ -439,12 +668,9 @@ __device__ __forceinline__ void hop_single(const Geom &g, const char *__restrict
     bool flip;
     const int64_t nb = hop_neighbour<MU, FWD>(g, s, c, flip);
     cplx<typename hop_elem<P>::type> psi[12];
-    cplx<T> u[9];
     T sgn = flip ? T(-1) : T(1);
     load_spinor_hop<P>(in, nb, psi, sgn);
-    if constexpr (FWD) load_link<P, LK, LNT>(U, g.ntiles, p, s, MU, u);
-    else load_link<P, LK, LNT>(U, g.ntiles, p ^ 1, nb, MU, u);
-    hop_chi<MU, S, !FWD>(psi, u, sgn, x0, x1);
+    link_chi<MU, S, !FWD, P, LK, LNT>(U, g.ntiles, FWD ? p : p ^ 1, FWD ? s : nb, psi, sgn, x0, x1);
 }
 
 // Sign S of the projector of hop H.
@@ -480,30 +706,36 @@ __device__ __forceinline__ void hop_direction(const Geom &g, const char *__restr
     const int64_t bwd = hop_neighbour<MU, false>(g, s, c, flip_b);
     cplx<T> f[6];
     if (face_f) {
-        cplx<T> h[6], u[9];
-        load_face<T>(face[0], s - (int64_t)(g.L[3] - 1) * g.st, h);
-        load_link<P, LK, LNT>(U, g.ntiles, p, s, MU, u);
-        half_mul<false>(u, h, h + 3, f, f + 3);
+        if constexpr (P == LQCD_F16) {
+            v2h hr[6], hi[6], u[6];
+            cplx<float> r2[3];
+            float fac;
+            load_face_forms(face[0], s - (int64_t)(g.L[3] - 1) * g.st, hr, hi, fac);
+            load_link_h<LNT>(U, g.ntiles, p, s, MU, u, r2);
+            half_mul_h<false>(hr, hi, u, r2, fac, f, f + 3);
+        } else {
+            cplx<T> h[6], u[9];
+            load_face<T>(face[0], s - (int64_t)(g.L[3] - 1) * g.st, h);
+            load_link<P, LK, LNT>(U, g.ntiles, p, s, MU, u);
+            half_mul<false>(u, h, h + 3, f, f + 3);
+        }
     } else {
         T sgn = flip_f ? T(-1) : T(1);
         cplx<typename hop_elem<P>::type> psi[12];
-        cplx<T> u[9];
         load_spinor_hop<P>(in, fwd, psi, sgn);
-        load_link<P, LK, LNT>(U, g.ntiles, p, s, MU, u);
-        hop_chi<MU, SF, false>(psi, u, sgn, f, f + 3);
+        link_chi<MU, SF, false, P, LK, LNT>(U, g.ntiles, p, s, psi, sgn, f, f + 3);
     }
     hop_fence<T, 6>(f);
     {
         cplx<T> b[6];
         if (face_b) {
-            load_face<T>(face[1], s, b);
+            if constexpr (P == LQCD_F16) load_face_h(face[1], s, b);
+            else load_face<T>(face[1], s, b);
         } else {
             T sgn = flip_b ? T(-1) : T(1);
             cplx<typename hop_elem<P>::type> psi[12];
-            cplx<T> u[9];
             load_spinor_hop<P>(in, bwd, psi, sgn);
-            load_link<P, LK, LNT>(U, g.ntiles, p ^ 1, bwd, MU, u);
-            hop_chi<MU, SB, true>(psi, u, sgn, b, b + 3);
+            link_chi<MU, SB, true, P, LK, LNT>(U, g.ntiles, p ^ 1, bwd, psi, sgn, b, b + 3);
         }
 #pragma unroll
         for (int a = 0; a < 3; ++a) {

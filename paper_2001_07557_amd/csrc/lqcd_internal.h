@@ -261,8 +261,8 @@ __device__ __forceinline__ void load_spinor(const char *__restrict__ base, int64
 }
 
 // Element type a hop reads spinors in: the arithmetic type, except binary16
-// storage, whose values stay binary16 until the projection (which adds them
-// with mixed-precision fused multiply-adds, so no separate conversion runs).
+// storage, whose stored values go unconverted into the hop's packed binary16
+// projection.
 template <int P> struct hop_elem { using type = typename real_of<P>::type; };
 template <> struct hop_elem<LQCD_F16> { using type = _Float16; };
 typedef _Float16 v2h __attribute__((ext_vector_type(2)));

@@ -161,7 +161,8 @@ def test_volume_limit_and_empty_vectors(lib):
     assert lib.lqcd_face_bytes(ctypes.byref(g4), 0) == 0  # 4^4: 32 sites per slice
     g8 = geom((8, 8, 8, 8))
     assert lib.lqcd_face_bytes(ctypes.byref(g8), 0) == 256 * 6 * 16
-    assert lib.lqcd_face_bytes(ctypes.byref(g8), 2) == 256 * 6 * 8
+    assert lib.lqcd_face_bytes(ctypes.byref(g8), 1) == 256 * 6 * 8
+    assert lib.lqcd_face_bytes(ctypes.byref(g8), 2) == 256 * 52
     assert lib.lqcd_hop_region(ctypes.byref(g8), 0, 2, a, b, None, u, t1, t2, 1.0, 0.0, 0, 0, 18,
                                None) == -1
     assert lib.lqcd_hop_region(ctypes.byref(g8), 0, 1, a, b, None, u, None, t2, 1.0, 0.0, 0, 0, 18,
