@@ -59,13 +59,20 @@ namespace lqcd {
 // 67.1, full-lattice FP64-18 M 4.39 -> 4.88 TB/s; at 32^4 FP64-18 78.4 ->
 // 79.8 and 78.3 -> 77.9, FP64-12 73.9 -> 72.7 and 73.8 -> 73.0 (not taken);
 // three blocks per CU +0.6 at 48^3x96, one block 57%; binary16 storage
-// (also 4-way) loses 8 points with it and keeps four.  LQCD_HOP_EXTRA_LDS
-// forces a value for every 4-way launch (ablations).
+// (also 4-way) loses 8 points with it and keeps four.  A both-parity launch
+// (full-lattice D_hop and M) keeps two tiles' links and both halves of psi
+// in play and takes the limit from V/2 >= 2^17: full-lattice FP64-18 M at
+// 24^4 4.82 -> 5.15 TB/s and at 32^4 4.67-4.73 -> 4.74-4.91 TB/s (two runs
+// each).  LQCD_HOP_EXTRA_LDS forces a value for every 4-way launch
+// (ablations).
 #ifndef LQCD_HOP_F64_LDS_EXTRA
 #define LQCD_HOP_F64_LDS_EXTRA 18432
 #endif
 #ifndef LQCD_HOP_F64_LDS_MIN_LOG2
 #define LQCD_HOP_F64_LDS_MIN_LOG2 20
+#endif
+#ifndef LQCD_HOP_F64_PAIRED_LDS_MIN_LOG2
+#define LQCD_HOP_F64_PAIRED_LDS_MIN_LOG2 17
 #endif
 #ifndef LQCD_HOP_EXTRA_LDS
 #define LQCD_HOP_EXTRA_LDS -1
@@ -636,7 +643,8 @@ int hop_launch(const HopArgs &a0, int prec, int link, bool dag, int nparity, hip
     const bool link_nt = LQCD_LINK_NT && !a.paired && spinors + links > INFINITY_CACHE_BYTES;
     a.stream = LQCD_HOP_STREAM >= 0 ? LQCD_HOP_STREAM : (out_nt ? 1 : 0) | (link_nt ? 2 : 0);
     a.lds_extra = LQCD_HOP_EXTRA_LDS >= 0 ? (uint32_t)LQCD_HOP_EXTRA_LDS
-                  : prec == LQCD_F64 && a.g.vh >= ((int64_t)1 << LQCD_HOP_F64_LDS_MIN_LOG2)
+                  : prec == LQCD_F64 && a.g.vh >= ((int64_t)1 << (a.paired ? LQCD_HOP_F64_PAIRED_LDS_MIN_LOG2
+                                                                               : LQCD_HOP_F64_LDS_MIN_LOG2))
                       ? (uint32_t)LQCD_HOP_F64_LDS_EXTRA
                       : 0u;
     dim3 grid((unsigned)(a.bpp * nparity));
