@@ -76,7 +76,9 @@ extern "C" {
 #define LQCD_F64   0
 #define LQCD_F32   1
 #define LQCD_F16   2       /* binary16 storage; spinors carry one FP32 scale
-                              per site (max |real| of the site) */
+                              per site (max |real| of the site); hopping-term
+                              launches take V/2 <= 44.7M sites (each parity's
+                              links below 4 GB), else LQCD_EINVAL */
 
 /* link storage: full 3x3 (18 reals) or rows 0 and 1 only (12 reals), with
    row 2 = conj(row0 x row1) rebuilt in registers (valid for SU(3) only) */

@@ -613,6 +613,7 @@ static void launch_l(const HopArgs &a, bool dag, bool hasy, int norm, dim3 grid,
 
 int hop_launch(const HopArgs &a0, int prec, int link, bool dag, int nparity, hipStream_t st,
                int region) {
+    if (prec == LQCD_F16 && a0.g.ntiles > F16_MAX_TILES) return LQCD_EINVAL;
     HopArgs a = a0;
     if (region < 0) {
         a.bpp = (a.g.vh + HOP_SITES - 1) / HOP_SITES;

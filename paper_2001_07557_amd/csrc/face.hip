@@ -74,6 +74,7 @@ extern "C" int lqcd_face_pack(const lqcd_geom_t *gg, void *face_fwd, void *face_
     Geom g;
     if (!make_geom(gg, &g) || !valid_link(prec, link)) return LQCD_EINVAL;
     if (g.st % TILE != 0) return LQCD_EINVAL;
+    if (prec == LQCD_F16 && g.ntiles > F16_MAX_TILES) return LQCD_EINVAL;
     if (out_par != LQCD_EVEN && out_par != LQCD_ODD) return LQCD_EINVAL;
     if (!face_fwd || !face_bwd || !in || !U || face_fwd == face_bwd) return LQCD_EINVAL;
     if (((uintptr_t)face_fwd | (uintptr_t)face_bwd | (uintptr_t)in | (uintptr_t)U) & 15)

@@ -362,9 +362,13 @@ template <bool NT>
 __device__ __forceinline__ void load_link_h(const char *__restrict__ U, int64_t ntiles, int p,
                                             int64_t s, int mu, v2h u[6], cplx<float> r2[3]) {
     const int lane = (int)(s & (TILE - 1));
-    const char *t = link_tile<LQCD_F16, 12>(U, ntiles, p, s >> TILE_SHIFT, mu);
-    const v4u q = stream_load<NT>(reinterpret_cast<const v4u *>(t) + lane);
-    const v2u q2 = stream_load<NT>(reinterpret_cast<const v2u *>(t + TILE * WORD) + lane);
+    // the parity's links from a 64-bit base (p is the same across a block),
+    // the tile and lane within it by a 32-bit offset (F16_MAX_TILES)
+    const char *up = U + (int64_t)p * ntiles * 4 * link_tile_bytes(LQCD_F16, 12);
+    const uint32_t toff = ((uint32_t)(s >> TILE_SHIFT) * 4u + (uint32_t)mu) * (uint32_t)link_tile_bytes(LQCD_F16, 12);
+    const v4u q = stream_load<NT>(reinterpret_cast<const v4u *>(up + (uint64_t)(toff + (uint32_t)lane * WORD)));
+    const v2u q2 = stream_load<NT>(
+        reinterpret_cast<const v2u *>(up + (uint64_t)(toff + TILE * WORD + (uint32_t)lane * 8u)));
     const uint32_t w[6] = {q.x, q.y, q.z, q.w, q2.x, q2.y};
     cplx<float> f[6];
 #pragma unroll

@@ -58,6 +58,12 @@ __host__ __device__ constexpr int link_tile_bytes(int prec, int link) {
                             : TILE * WORD + TILE * 8;
 }
 
+// binary16 hops address a parity's links and a half spinor field by 32-bit
+// offsets, so each must stay below 4 GB: at most this many tiles per parity
+// (V/2 <= 44.7M sites); larger binary16 hop launches return LQCD_EINVAL
+constexpr int64_t F16_MAX_TILES = 0xffffffffLL / (4 * link_tile_bytes(LQCD_F16, 12));
+static_assert(F16_MAX_TILES * spinor_tile_bytes(LQCD_F16) <= 0xffffffffLL, "binary16 spinor offsets");
+
 inline bool valid_prec(int p) { return p == LQCD_F64 || p == LQCD_F32 || p == LQCD_F16; }
 inline bool valid_link(int prec, int link) {
     if (link != 18 && link != 12) return false;
@@ -275,11 +281,13 @@ __device__ __forceinline__ void load_spinor_hop(const char *__restrict__ base, i
                                                 cplx<typename hop_elem<P>::type> v[12],
                                                 typename real_of<P>::type &factor) {
     if constexpr (P == LQCD_F16) {
-        const int64_t tile = s >> TILE_SHIFT;
+        // 32-bit offsets from the field's base (binary16 hop launches are
+        // limited to fields below 4 GB): the loads take the base from
+        // scalar registers and need no 64-bit address arithmetic
         const int lane = (int)(s & (TILE - 1));
-        const char *t = base + tile * spinor_tile_bytes(P);
-        const v4u *w = reinterpret_cast<const v4u *>(t) + lane;
-        factor *= reinterpret_cast<const float *>(t + 3 * TILE * WORD)[lane];
+        const uint32_t toff = (uint32_t)(s >> TILE_SHIFT) * (uint32_t)spinor_tile_bytes(P);
+        const v4u *w = reinterpret_cast<const v4u *>(base + (uint64_t)(toff + (uint32_t)lane * WORD));
+        factor *= *reinterpret_cast<const float *>(base + (uint64_t)(toff + 3u * TILE * WORD + (uint32_t)lane * 4u));
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
             v4u q = w[k * TILE];

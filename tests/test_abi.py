@@ -170,6 +170,10 @@ def test_volume_limit_and_empty_vectors(lib):
     assert lib.lqcd_hop_region(ctypes.byref(g4), 0, 0, a, b, None, u, None, None, 1.0, 0.0, 0, 0,
                                18, None) == -1
     assert lib.lqcd_face_pack(ctypes.byref(g8), t1, t1, b, u, 0, 0, 0, 18, None) == -1
+    # binary16 hops address a parity's links by 32-bit offsets: V/2 <= 44.7M sites
+    g100 = geom((100, 100, 100, 100))
+    assert lib.lqcd_meo(ctypes.byref(g100), a, b, None, u, 1.0, 0.0, 0, 2, 12, None) == -1
+    assert lib.lqcd_face_pack(ctypes.byref(g100), t1, t2, b, u, 0, 0, 2, 12, None) == -1
     # SU(3) product: binary16 is not a product precision
     assert lib.lqcd_su3_mul(ctypes.byref(g4), a, b, ctypes.c_void_p(12288), 0, 0, 2, 12, None) == -1
 
