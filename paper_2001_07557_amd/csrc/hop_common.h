@@ -356,6 +356,20 @@ __device__ __forceinline__ float mix2(cplx<float> r, v2h v, float c) {
     return fmaf(r.re, (float)v.x, fmaf(r.im, (float)v.y, c));
 }
 
+// conj(a b - c d) of binary16 complex numbers in FP32, every product a
+// mixed-precision FMA on the stored halves (no separate conversion)
+__device__ __forceinline__ cplx<float> conj_cross_h(v2h a, v2h b, v2h c, v2h d) {
+    float re = fmaf((float)c.y, (float)d.y, 0.f);
+    re = fmaf(-(float)c.x, (float)d.x, re);
+    re = fmaf(-(float)a.y, (float)b.y, re);
+    re = fmaf((float)a.x, (float)b.x, re);
+    float im = fmaf((float)c.x, (float)d.y, 0.f);
+    im = fmaf((float)c.y, (float)d.x, im);
+    im = fmaf(-(float)a.x, (float)b.y, im);
+    im = fmaf(-(float)a.y, (float)b.x, im);
+    return {re, im};
+}
+
 // A binary16 12-real link: rows 0 and 1 as stored (re, im pairs), row 2 =
 // conj(row0 x row1) in FP32.
 template <bool NT>
@@ -370,15 +384,11 @@ __device__ __forceinline__ void load_link_h(const char *__restrict__ U, int64_t 
     const v2u q2 = stream_load<NT>(
         reinterpret_cast<const v2u *>(up + (uint64_t)(toff + TILE * WORD + (uint32_t)lane * 8u)));
     const uint32_t w[6] = {q.x, q.y, q.z, q.w, q2.x, q2.y};
-    cplx<float> f[6];
 #pragma unroll
-    for (int j = 0; j < 6; ++j) {
-        u[j] = __builtin_bit_cast(v2h, w[j]);
-        f[j] = {(float)u[j].x, (float)u[j].y};
-    }
-    r2[0] = conj_cross(f[1], f[5], f[2], f[4]);
-    r2[1] = conj_cross(f[2], f[3], f[0], f[5]);
-    r2[2] = conj_cross(f[0], f[4], f[1], f[3]);
+    for (int j = 0; j < 6; ++j) u[j] = __builtin_bit_cast(v2h, w[j]);
+    r2[0] = conj_cross_h(u[1], u[5], u[2], u[4]);
+    r2[1] = conj_cross_h(u[2], u[3], u[0], u[5]);
+    r2[2] = conj_cross_h(u[0], u[4], u[1], u[3]);
 }
 
 // The projected half-spinor of one hop, rows 0 and 1 of (1 + S g_mu) psi,

@@ -493,6 +493,28 @@ def test_full_size_sampled(dims, prec, link):
 
 
 @pytest.mark.slow
+@pytest.mark.parametrize("prec,link", [(P.F64, 18), (P.F64, 12), (P.F32, 18), (P.F32, 12), (P.F16, 12)])
+def test_every_site_haar_24x4(prec, link):
+    """Every output site of the 24^4 even-odd hop (bricks of two-plane
+    groups, four z-slabs shared by the eight XCDs) with Haar links against
+    the oracle's whole field, per site and norm-wise: D_eo and the adjoint
+    D_oe."""
+    dims = (24, 24, 24, 24)
+    lat = P.Lattice(dims)
+    U, psi, y, Ur, psr, yr, tdt = eo_case(prec, link, dims, k=7)
+    Uf = P.pack_gauge(lat, dev(U).to(tdt), prec, link)
+    tol = {P.F64: TOL64, P.F32: TOL32, P.F16: TOL16}[prec]
+    for out_par, fn, dag in ((P.EVEN, P.meo, False), (P.ODD, P.moe, True)):
+        inp = P.pack_spinor(lat, dev(psi).to(tdt), prec, 1 - out_par)
+        out = P.new_spinor(lat, prec, out_par)
+        fn(out, inp, Uf, dagger=dag)
+        got = host(P.unpack_spinor(out))
+        want = want_eo(prec, psi, psr, Ur, out_par, dag)
+        assert rel(got, want) < tol
+        assert site_rel(got, want) < max(tol, 1e-12)
+
+
+@pytest.mark.slow
 @pytest.mark.parametrize("dims", [(32, 32, 32, 32), (32, 32, 36, 16), (18, 18, 42, 40),
                                   (24, 24, 24, 24)])
 @pytest.mark.parametrize("prec,link", [(P.F64, 18), (P.F32, 12), (P.F16, 12)])
