@@ -170,8 +170,8 @@ __device__ __forceinline__ double hop_epilogue(const HopArgs &a, int p, int64_t 
 static_assert(offsetof(HopArgs, cg_x) <= 5 * 64 && sizeof(HopArgs) <= 6 * 64,
               "the fields read first span five lines, the CG-update fields a sixth");
 static_assert(offsetof(HopArgs, bpp) / 64 == 0 &&
-                  (offsetof(HopArgs, g) + offsetof(Geom, vh)) / 64 == 1 &&
-                  (offsetof(HopArgs, g) + offsetof(Geom, dz) + offsetof(FastDiv, m)) / 64 == 2 &&
+                  (offsetof(HopArgs, g) + offsetof(Geom, lxh)) / 64 == 1 &&
+                  (offsetof(HopArgs, g) + offsetof(Geom, vh)) / 64 == 2 &&
                   offsetof(HopArgs, in) / 64 == 3 && offsetof(HopArgs, stream) / 64 == 4,
               "one touched field per line of the launch arguments");
 
@@ -185,7 +185,7 @@ __device__ __forceinline__ int64_t hop_site_index(const HopArgs &a, int lane, in
     // one field from each 64-byte line of the arguments, needed before
     // anything else: the lines come in with one scalar-cache miss instead of
     // one after each dependent step
-    asm volatile("" ::"s"(a.bpp), "s"(a.g.vh), "s"(a.g.dz.m), "s"(a.in[0]), "s"(a.stream));
+    asm volatile("" ::"s"(a.bpp), "s"(a.g.lxh), "s"(a.g.vh), "s"(a.in[0]), "s"(a.stream));
 #endif
     const uint32_t bx = blockIdx.x;
     blk = LQCD_HOP_XCD ? xcd_block(bx, a.nblk) : (int64_t)bx;
@@ -617,7 +617,9 @@ int hop_launch(const HopArgs &a0, int prec, int link, bool dag, int nparity, hip
     HopArgs a = a0;
     if (region < 0) {
         a.bpp = (a.g.vh + HOP_SITES - 1) / HOP_SITES;
-        a.brick = make_brick(a.g, brick_plan(a.g, prec));
+        a.brick = make_brick(a.g, brick_plan(a.g, prec,
+                                             nparity == 2 && LQCD_HOP_PAIRED ? 2
+                                             : nparity == 1 && LQCD_BRICK_BAND_EO ? 1 : 0));
         a.face[0] = a.face[1] = nullptr;
     } else {
         // interior slices 1 .. Lt-2, or boundary slices 0 and Lt-1

@@ -58,6 +58,26 @@ constexpr int64_t BRICK_L2_BUDGET = (int64_t)LQCD_BRICK_BUDGET_KB << 10;
 #ifndef LQCD_BRICK_MIN_LOG2
 #define LQCD_BRICK_MIN_LOG2 17
 #endif
+// y-bands of an FP64 or FP32 both-parity launch (full-lattice D_hop and M).
+// Such a launch keeps both halves of psi and its links in play, so the three
+// t-slices of a z-slab that rule 1 keeps in an XCD's L2 are twice the
+// even-odd footprint (48^3x96 FP64: 8 MB).  Where they exceed LQCD_BRICK_BAND_KB, each slab is
+// cut into y-bands of whole rows (z-groups of one plane only), walked in t
+// one after the other.  Measured (full-lattice M, TB/s, slab -> bands, four
+// and two runs): 48^3x96 FP64-18 4.87-4.94 -> 5.11-5.23 (six bands), FP32-18
+// 5.02-5.16 -> 5.15-5.31 (three); 32^4 FP64-18 4.78-4.93 -> 4.95-5.04 (two);
+// fetched bytes over algorithmic 1.58x -> 1.16x and 1.41x -> 1.12x (FP64).
+// Bands on the even-odd hop cut its 48^3x96 FP64 fetch from 1.28x to 1.07x
+// yet run 1.8 points slower (the re-fetched slices are Infinity Cache
+// hits), and bands across a two-plane z-group (24^4) lose 5%, so neither is
+// done.  0 switches the bands off; LQCD_BRICK_BAND_EO = 1 gives the even-odd
+// launches bands too (ablation).
+#ifndef LQCD_BRICK_BAND_KB
+#define LQCD_BRICK_BAND_KB 1536
+#endif
+#ifndef LQCD_BRICK_BAND_EO
+#define LQCD_BRICK_BAND_EO 0
+#endif
 // number of z-bricks rule 1 aims for with FP64 fields (ablation switch; 8
 // gives every XCD one slab, 16 two thinner ones walked one after the other)
 #ifndef LQCD_BRICK_NB_F64
@@ -88,6 +108,8 @@ __device__ __forceinline__ void hop_fence(cplx<T> acc[N]) {
 struct Brick {
     FastDiv pt, bz, lt;
     int lz;
+    FastDiv nyb;    // y-bands per z-group, walked one after the other
+    uint32_t ptg;   // tiles per z-group (pt = ptg / nyb tiles per band)
     // t-slices visited: t0, t0 + tstep, ... (lt of them); a whole-lattice
     // launch has t0 = 0, tstep = 1, a region launch (interior or boundary
     // slices of a t decomposition) other values
@@ -130,18 +152,20 @@ struct HopArgs {
 };
 
 // Tile visited by logical block b (within one parity).  With bricks of bz
-// z-groups the order is (z-brick, t, z-group in brick, tile in group): the
-// three t-slices of a brick that one output slice touches stay in the XCD's L2,
-// where the plain order would revisit each input slice from memory for the
-// t-neighbours of the slices before and after it.
+// z-groups the order is (z-brick, y-band, t, z-group in brick, tile in band):
+// the three t-slices of a brick that one output slice touches stay in the
+// XCD's L2, where the plain order would revisit each input slice from memory
+// for the t-neighbours of the slices before and after it.
 __device__ __forceinline__ int64_t brick_order(uint32_t b, const Brick &k) {
-    const uint32_t r1 = fdiv(b, k.pt);   // (z-group, t) in traversal order
-    const uint32_t r2 = fdiv(r1, k.bz);  // (brick, t)
-    const uint32_t zc = fdiv(r2, k.lt);  // brick
+    const uint32_t r1 = fdiv(b, k.pt);    // (z-group, t) in traversal order
+    const uint32_t r2 = fdiv(r1, k.bz);   // (brick, band, t)
+    const uint32_t r3 = fdiv(r2, k.lt);   // (brick, band)
+    const uint32_t zc = fdiv(r3, k.nyb);  // brick
     const uint32_t tile = b - r1 * k.pt.d;
     const uint32_t zi = r1 - r2 * k.bz.d;
-    const uint32_t t = k.t0 + (r2 - zc * k.lt.d) * k.tstep;
-    return (int64_t)((t * k.lz + zc * k.bz.d + zi) * k.pt.d + tile);
+    const uint32_t t = k.t0 + (r2 - r3 * k.lt.d) * k.tstep;
+    const uint32_t band = r3 - zc * k.nyb.d;
+    return (int64_t)((t * k.lz + zc * k.bz.d + zi) * k.ptg + band * k.pt.d + tile);
 }
 
 __device__ __forceinline__ int64_t brick_tile(const HopArgs &a, uint32_t b) {
@@ -152,15 +176,18 @@ __device__ __forceinline__ int64_t brick_tile(const HopArgs &a, uint32_t b) {
 // z-planes whose sites fill whole tiles, usually one plane) form a unit; a
 // brick is bz z-groups and all t.  bz = 0: plain order.
 struct BrickPlan {
-    int pt;  // tiles per z-group
-    int bz;  // z-groups per brick
-    int lz;  // z-groups in Lz
+    int pt;      // tiles per z-group
+    int bz;      // z-groups per brick
+    int lz;      // z-groups in Lz
+    int ny = 1;  // y-bands per z-group
 };
 
 // See the rules next to LQCD_BRICK_MODE.  Rule 1 cuts Lz into 8 bricks (one
 // per XCD), or into 4 when the z-groups do not divide by 8 (two XCDs then
-// share a brick, each taking half of its t range).
-inline BrickPlan brick_plan(const Geom &g, int prec) {
+// share a brick, each taking half of its t range).  `halves`: 2 for the plan
+// of a both-parity launch, which may add y-bands (LQCD_BRICK_BAND_KB); 1 for
+// an even-odd launch of an ablation build that bands those too; 0 no bands.
+inline BrickPlan brick_plan(const Geom &g, int prec, int halves = 0) {
     BrickPlan k{0, 0, 0};
     if (!LQCD_HOP_BRICK || !((LQCD_BRICK_PRECS >> prec) & 1)) return k;
     // small lattices live in the caches anyway: only half-lattices of at
@@ -177,6 +204,16 @@ inline BrickPlan brick_plan(const Geom &g, int prec) {
         for (int nb : {nb0, nb0 / 2}) {
             if (lz % nb == 0 && lz / nb >= 2) {
                 k = {(int)pt, lz / nb, lz};
+                // three t-slices of the slab, of each half the launch reads
+                const int64_t fp = halves * 3 * (int64_t)k.bz * pt * spinor_tile_bytes(prec);
+                if (halves > 0 && prec != LQCD_F16 && gz == 1 &&
+                    fp > ((int64_t)LQCD_BRICK_BAND_KB << 10))
+                    for (int ny = 2; ny <= pt; ++ny)
+                        if (pt % ny == 0 && (pt / ny * TILE) % g.lxh == 0 &&
+                            fp / ny <= ((int64_t)LQCD_BRICK_BAND_KB << 10)) {
+                            k.ny = ny;
+                            break;
+                        }
                 return k;
             }
         }
@@ -199,11 +236,15 @@ inline Brick make_brick(const Geom &g, const BrickPlan &b) {
         k.bz = make_fastdiv(1);
         k.lt = make_fastdiv((1u << 31) - 1);
         k.lz = 1;
+        k.nyb = make_fastdiv(1);
+        k.ptg = 1;
     } else {
-        k.pt = make_fastdiv((uint32_t)b.pt);
+        k.pt = make_fastdiv((uint32_t)(b.pt / b.ny));
         k.bz = make_fastdiv((uint32_t)b.bz);
         k.lt = make_fastdiv((uint32_t)g.L[3]);
         k.lz = b.lz;
+        k.nyb = make_fastdiv((uint32_t)b.ny);
+        k.ptg = (uint32_t)b.pt;
     }
     k.t0 = 0;
     k.tstep = 1;
@@ -220,6 +261,7 @@ inline Brick make_region_brick(const Geom &g, const BrickPlan &b, int t0, int ts
         k.pt = make_fastdiv((uint32_t)(g.st / TILE));
         k.bz = make_fastdiv(1);
         k.lz = 1;
+        k.ptg = (uint32_t)(g.st / TILE);
     }
     k.lt = make_fastdiv((uint32_t)nt);
     k.t0 = (uint32_t)t0;
