@@ -196,9 +196,10 @@ int lqcd_moe(const lqcd_geom_t *g, void *out_o, const void *in_e, const void *y_
  * arithmetic precision as tiles of 64 sites of six complex numbers (FP64
  * 96 bytes per site, FP32 48); for binary16 storage face_fwd holds the
  * binary16 half-spinor in units of the site scale, with that scale times
- * bc[3] kept apart (52 bytes per site), and face_bwd six FP32 complex numbers
- * in the same 52-byte tiles, so the receiver's arithmetic is the unsplit
- * hop's; lqcd_face_bytes gives the size of one face.  On one
+ * bc[3] kept apart (52 bytes per site), and face_bwd the six FP32 complex
+ * numbers of U_t(y)^dag times that half-spinor with the same kind of factor
+ * kept apart, in the same 52-byte tiles, so the receiver's arithmetic is the
+ * unsplit hop's; lqcd_face_bytes gives the size of one face.  On one
  * GPU the faces of this lattice's own t wrap stand in for the neighbours'.
  * lqcd_hop_region computes the hop (as lqcd_meo / lqcd_moe: out = alpha
  * D in + beta y) on region 0, the interior slices 1 .. Lt-2 (no face

@@ -11,7 +11,9 @@
 // same code and the same arithmetic as inside the fused hop, so a boundary
 // launch that reads them reproduces the unsplit hop bit for bit (binary16
 // storage: the forward face holds the packed binary16 half-spinor and the
-// neighbour's scale times s, which the receiver applies after its link).
+// neighbour's scale times s, which the receiver applies after its link; the
+// backward face holds U^dag times the half-spinor and, apart, the same kind
+// of factor, which the receiver folds into its sums as the unsplit hop does).
 
 #include "lqcd_internal.h"
 #include "hop_common.h"
@@ -52,8 +54,8 @@ __global__ __launch_bounds__(FACE_BLOCK) void face_pack_k(Geom g, char *fwd_face
         const int64_t y = (int64_t)(g.L[3] - 1) * g.st + j;
         cplx<T> x[6];
         load_spinor_hop<P>(in, y, psi, sgn);
-        link_chi<3, -SF, true, P, LK, false>(U, g.ntiles, q, y, psi, sgn, x, x + 3);
-        if constexpr (P == LQCD_F16) store_face_h(bwd_face, j, x);
+        link_chi<3, -SF, true, P, LK, false, P != LQCD_F16>(U, g.ntiles, q, y, psi, sgn, x, x + 3);
+        if constexpr (P == LQCD_F16) store_face_h(bwd_face, j, x, sgn);
         else store_face<T>(bwd_face, j, x);
     }
 }

@@ -457,8 +457,9 @@ __device__ __forceinline__ void half_forms_h(const cplx<_Float16> psi[12], v2h h
 }
 
 // factor (U h) or factor (U^dag h) for the two colour vectors of a
-// half-spinor in packed forms: x0 from row 0, x1 from row 1.
-template <bool UDAG>
+// half-spinor in packed forms: x0 from row 0, x1 from row 1 (SCALE false:
+// U h or U^dag h, the caller applies the factor).
+template <bool UDAG, bool SCALE = true>
 __device__ __forceinline__ void half_mul_h(const v2h hr[6], const v2h hi[6], const v2h u[6],
                                            const cplx<float> r2[3], float factor,
                                            cplx<float> x0[3], cplx<float> x1[3]) {
@@ -472,31 +473,31 @@ __device__ __forceinline__ void half_mul_h(const v2h hr[6], const v2h hi[6], con
             for (int a = 0; a < 2; ++a) {
                 const float re = dot2h(u[3 * a + 2], fr[2], dot2h(u[3 * a + 1], fr[1], dot2h0(u[3 * a], fr[0])));
                 const float im = dot2h(u[3 * a + 2], fi[2], dot2h(u[3 * a + 1], fi[1], dot2h0(u[3 * a], fi[0])));
-                x[a] = {mul_nc(factor, re), mul_nc(factor, im)};
+                x[a] = SCALE ? cplx<float>{mul_nc(factor, re), mul_nc(factor, im)} : cplx<float>{re, im};
             }
             const float re = mix2(r2[2], fr[2], mix2(r2[1], fr[1], mix2(r2[0], fr[0], 0.f)));
             const float im = mix2(r2[2], fi[2], mix2(r2[1], fi[1], mix2(r2[0], fi[0], 0.f)));
-            x[2] = {mul_nc(factor, re), mul_nc(factor, im)};
+            x[2] = SCALE ? cplx<float>{mul_nc(factor, re), mul_nc(factor, im)} : cplx<float>{re, im};
         } else {
             // U^dag[a][b] = conj(U[b][a]): u[a], u[3 + a] and r2[a]
 #pragma unroll
             for (int a = 0; a < 3; ++a) {
                 const float re = dot2h(u[3 + a], fr[1], dot2h(u[a], fr[0], mix2(r2[a], fr[2], 0.f)));
                 const float im = dot2h(u[3 + a], fi[1], dot2h(u[a], fi[0], mix2(r2[a], fi[2], 0.f)));
-                x[a] = {mul_nc(factor, re), mul_nc(factor, im)};
+                x[a] = SCALE ? cplx<float>{mul_nc(factor, re), mul_nc(factor, im)} : cplx<float>{re, im};
             }
         }
     }
 }
 
 // One hop on binary16 storage: the two colour vectors chi0, chi1.
-template <int MU, int S, bool UDAG>
+template <int MU, int S, bool UDAG, bool SCALE = true>
 __device__ __forceinline__ void hop_chi_h(const cplx<_Float16> psi[12], const v2h u[6],
                                           const cplx<float> r2[3], float factor,
                                           cplx<float> x0[3], cplx<float> x1[3]) {
     v2h hr[6], hi[6];
     half_forms_h<MU, S, UDAG>(psi, hr, hi);
-    half_mul_h<UDAG>(hr, hi, u, r2, factor, x0, x1);
+    half_mul_h<UDAG, SCALE>(hr, hi, u, r2, factor, x0, x1);
 }
 
 // Project with (1 + S g_mu), apply the boundary sign and multiply by U (or
@@ -513,7 +514,7 @@ __device__ __forceinline__ void hop_chi(const cplx<T> psi[12], const cplx<T> u[9
 // vectors of one hop from the neighbour spinor psi (binary16 storage: the
 // packed path above; factor = boundary sign, times the site scale for
 // binary16).
-template <int MU, int S, bool UDAG, int P, int LK, bool LNT>
+template <int MU, int S, bool UDAG, int P, int LK, bool LNT, bool SCALE = true>
 __device__ __forceinline__ void link_chi(const char *__restrict__ U, int64_t ntiles, int q,
                                          int64_t y, const cplx<typename hop_elem<P>::type> psi[12],
                                          typename real_of<P>::type factor,
@@ -523,7 +524,7 @@ __device__ __forceinline__ void link_chi(const char *__restrict__ U, int64_t nti
         v2h u[6];
         cplx<float> r2[3];
         load_link_h<LNT>(U, ntiles, q, y, MU, u, r2);
-        hop_chi_h<MU, S, UDAG>(psi, u, r2, factor, x0, x1);
+        hop_chi_h<MU, S, UDAG, SCALE>(psi, u, r2, factor, x0, x1);
     } else {
         cplx<typename real_of<P>::type> u[9];
         load_link<P, LK, LNT>(U, ntiles, q, y, MU, u);
@@ -614,22 +615,28 @@ __device__ __forceinline__ void load_face_forms(const char *__restrict__ f, int6
     factor = reinterpret_cast<const float *>(t + 3 * TILE * WORD)[lane];
 }
 
-__device__ __forceinline__ void store_face_h(char *__restrict__ f, int64_t j, const cplx<float> v[6]) {
+__device__ __forceinline__ void store_face_h(char *__restrict__ f, int64_t j, const cplx<float> v[6],
+                                             float factor) {
     const int lane = (int)(j & (TILE - 1));
-    v4f *w = reinterpret_cast<v4f *>(f + (j >> TILE_SHIFT) * FACE_H_TILE) + lane;
+    char *t = f + (j >> TILE_SHIFT) * FACE_H_TILE;
+    v4f *w = reinterpret_cast<v4f *>(t) + lane;
 #pragma unroll
     for (int k = 0; k < 3; ++k) w[k * TILE] = v4f{v[2 * k].re, v[2 * k].im, v[2 * k + 1].re, v[2 * k + 1].im};
+    reinterpret_cast<float *>(t + 3 * TILE * WORD)[lane] = factor;
 }
 
-__device__ __forceinline__ void load_face_h(const char *__restrict__ f, int64_t j, cplx<float> v[6]) {
+__device__ __forceinline__ void load_face_h(const char *__restrict__ f, int64_t j, cplx<float> v[6],
+                                            float &factor) {
     const int lane = (int)(j & (TILE - 1));
-    const v4f *w = reinterpret_cast<const v4f *>(f + (j >> TILE_SHIFT) * FACE_H_TILE) + lane;
+    const char *t = f + (j >> TILE_SHIFT) * FACE_H_TILE;
+    const v4f *w = reinterpret_cast<const v4f *>(t) + lane;
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
         const v4f d = w[k * TILE];
         v[2 * k] = {d.x, d.y};
         v[2 * k + 1] = {d.z, d.w};
     }
+    factor = reinterpret_cast<const float *>(t + 3 * TILE * WORD)[lane];
 }
 
 // Bytes of one face buffer (one t-slice of one parity) for storage precision prec.
@@ -705,8 +712,14 @@ __device__ __forceinline__ void hop_single(const Geom &g, const char *__restrict
                 return;
             }
             cplx<T> h[6];
-            if constexpr (P == LQCD_F16) load_face_h(face[1], s, h);
-            else load_face<T>(face[FWD ? 0 : 1], FWD ? s - (int64_t)(g.L[3] - 1) * g.st : s, h);
+            if constexpr (P == LQCD_F16) {
+                float fb;
+                load_face_h(face[1], s, h, fb);
+#pragma unroll
+                for (int k = 0; k < 6; ++k) h[k] = {mul_nc(fb, h[k].re), mul_nc(fb, h[k].im)};
+            } else {
+                load_face<T>(face[FWD ? 0 : 1], FWD ? s - (int64_t)(g.L[3] - 1) * g.st : s, h);
+            }
             if constexpr (FWD) {
                 cplx<T> u[9];
                 load_link<P, LK, LNT>(U, g.ntiles, p, s, MU, u);
@@ -783,22 +796,37 @@ __device__ __forceinline__ void hop_direction(const Geom &g, const char *__restr
     }
     hop_fence<T, 6>(f);
     {
+        // binary16: the backward colour vectors stay unscaled and the
+        // neighbour's factor enters the sums as an FMA
         cplx<T> b[6];
+        T fb = T(1);
         if (face_b) {
-            if constexpr (P == LQCD_F16) load_face_h(face[1], s, b);
+            if constexpr (P == LQCD_F16) load_face_h(face[1], s, b, fb);
             else load_face<T>(face[1], s, b);
         } else {
             T sgn = flip_b ? T(-1) : T(1);
             cplx<typename hop_elem<P>::type> psi[12];
             load_spinor_hop<P>(in, bwd, psi, sgn);
-            link_chi<MU, SB, true, P, LK, LNT>(U, g.ntiles, p ^ 1, bwd, psi, sgn, b, b + 3);
+            link_chi<MU, SB, true, P, LK, LNT, P != LQCD_F16>(U, g.ntiles, p ^ 1, bwd, psi, sgn, b, b + 3);
+            if constexpr (P == LQCD_F16) fb = sgn;
         }
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
-            acc[a] = f[a] + b[a];
-            acc[3 + a] = f[3 + a] + b[3 + a];
-            acc[PR::a0 * 3 + a] = mul_unit<r0>(f[a] - b[a]);
-            acc[PR::a1 * 3 + a] = mul_unit<r1>(f[3 + a] - b[3 + a]);
+            if constexpr (P == LQCD_F16) {
+                const cplx<T> s0 = {fmaf(fb, b[a].re, f[a].re), fmaf(fb, b[a].im, f[a].im)};
+                const cplx<T> s1 = {fmaf(fb, b[3 + a].re, f[3 + a].re), fmaf(fb, b[3 + a].im, f[3 + a].im)};
+                const cplx<T> d0 = {fmaf(-fb, b[a].re, f[a].re), fmaf(-fb, b[a].im, f[a].im)};
+                const cplx<T> d1 = {fmaf(-fb, b[3 + a].re, f[3 + a].re), fmaf(-fb, b[3 + a].im, f[3 + a].im)};
+                acc[a] = s0;
+                acc[3 + a] = s1;
+                acc[PR::a0 * 3 + a] = mul_unit<r0>(d0);
+                acc[PR::a1 * 3 + a] = mul_unit<r1>(d1);
+            } else {
+                acc[a] = f[a] + b[a];
+                acc[3 + a] = f[3 + a] + b[3 + a];
+                acc[PR::a0 * 3 + a] = mul_unit<r0>(f[a] - b[a]);
+                acc[PR::a1 * 3 + a] = mul_unit<r1>(f[3 + a] - b[3 + a]);
+            }
         }
     }
     hop_fence<T, 12>(acc);
