@@ -61,17 +61,18 @@ constexpr int64_t BRICK_L2_BUDGET = (int64_t)LQCD_BRICK_BUDGET_KB << 10;
 // y-bands of an FP64 or FP32 both-parity launch (full-lattice D_hop and M).
 // Such a launch keeps both halves of psi and its links in play, so the three
 // t-slices of a z-slab that rule 1 keeps in an XCD's L2 are twice the
-// even-odd footprint (48^3x96 FP64: 8 MB).  Where they exceed LQCD_BRICK_BAND_KB, each slab is
-// cut into y-bands of whole rows (z-groups of one plane only), walked in t
-// one after the other.  Measured (full-lattice M, TB/s, slab -> bands, four
-// and two runs): 48^3x96 FP64-18 4.87-4.94 -> 5.11-5.23 (six bands), FP32-18
-// 5.02-5.16 -> 5.15-5.31 (three); 32^4 FP64-18 4.78-4.93 -> 4.95-5.04 (two);
-// fetched bytes over algorithmic 1.58x -> 1.16x and 1.41x -> 1.12x (FP64).
-// Bands on the even-odd hop cut its 48^3x96 FP64 fetch from 1.28x to 1.07x
-// yet run 1.8 points slower (the re-fetched slices are Infinity Cache
-// hits), and bands across a two-plane z-group (24^4) lose 5%, so neither is
-// done.  0 switches the bands off; LQCD_BRICK_BAND_EO = 1 gives the even-odd
-// launches bands too (ablation).
+// even-odd footprint (48^3x96 FP64: 8 MB).  Where they exceed
+// LQCD_BRICK_BAND_KB, each slab is cut into y-bands of whole rows (z-groups
+// of one plane only), walked in t one after the other.  Measured
+// (full-lattice M, TB/s, slab -> bands, four and two runs): 48^3x96 FP64-18
+// 4.87-4.94 -> 5.11-5.23 (six bands), FP32-18 5.02-5.16 -> 5.15-5.31
+// (three); 32^4 FP64-18 4.78-4.93 -> 4.95-5.04 (two); fetched bytes over
+// algorithmic 1.58x -> 1.16x and 1.41x -> 1.12x (FP64).  Bands on the
+// even-odd hop cut its 48^3x96 FP64 fetch from 1.27-1.35x to 1.06-1.08x yet
+// run 1.5-3.2 points slower (the slices whole slabs fetch again come from
+// the Infinity Cache), and bands across a two-plane z-group (24^4) lose 5%,
+// so neither is done.  0 switches the bands off; LQCD_BRICK_BAND_EO = 1
+// gives the even-odd launches bands too (ablation).
 #ifndef LQCD_BRICK_BAND_KB
 #define LQCD_BRICK_BAND_KB 1536
 #endif
