@@ -43,6 +43,38 @@ __global__ __launch_bounds__(GEN_BLOCK) void colour_mul_k(Geom g, char *out, con
     store_spinor<P>(out + p * hb, s, w);
 }
 
+// FP64: one spin of one site per thread, a block = the four spins of one
+// 64-site tile (wave = spin); the four waves read the same link words, the
+// later ones from the L2, and each holds a third of the spinor registers.
+template <int LK, bool ADJ>
+__global__ __launch_bounds__(GEN_BLOCK) void colour_mul_f64_k(Geom g, char *out, const char *in,
+                                                              const char *U, int64_t hb, int mu,
+                                                              int64_t tpp) {
+    const int64_t blk = xcd_block(blockIdx.x, gridDim.x);
+    const int p = blk >= tpp ? 1 : 0;
+    const int lane = threadIdx.x & 63;
+    const int sp = threadIdx.x >> 6;
+    const int64_t s = (blk - p * tpp) * TILE + lane;
+    if (s >= g.vh) return;
+    cplx<double> u[9];
+    load_link<LQCD_F64, LK, false>(U, g.ntiles, p, s, mu, u);
+    const int64_t toff = (s >> TILE_SHIFT) * spinor_tile_bytes(LQCD_F64);
+    const v2d *w = reinterpret_cast<const v2d *>(in + p * hb + toff) + lane;
+    v2d *o = reinterpret_cast<v2d *>(out + p * hb + toff) + lane;
+    cplx<double> c[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const v2d d = w[(3 * sp + a) * TILE];
+        c[a] = {d.x, d.y};
+    }
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const cplx<double> r = ADJ ? cdot3c(u[a], c[0], u[3 + a], c[1], u[6 + a], c[2])
+                                   : cdot3(u[3 * a], c[0], u[3 * a + 1], c[1], u[3 * a + 2], c[2]);
+        o[(3 * sp + a) * TILE] = v2d{r.re, r.im};
+    }
+}
+
 // acc(x) (+)= (1 + S g_mu) in(x): rows 0 and 1 of the projection and the two
 // rows that follow from them (the projector has rank two).
 template <int P, int MU, int S>
@@ -104,7 +136,17 @@ extern "C" int lqcd_colour_mul(const lqcd_geom_t *gg, void *out, const void *in,
 #define LQCD_CMUL(PR, LK)                                                                        \
     if (adjoint) colour_mul_k<PR, LK, true><<<grid, block, 0, st>>>(g, o, i, u, hb, mu, bpp);    \
     else colour_mul_k<PR, LK, false><<<grid, block, 0, st>>>(g, o, i, u, hb, mu, bpp);
-    if (prec == LQCD_F64) {
+    if (prec == LQCD_F64 && !LQCD_LAYOUT_AOS) {
+        const int64_t tpp = g.ntiles;
+        dim3 g4((unsigned)(2 * tpp)), b4(GEN_BLOCK);
+        if (link == 18) {
+            if (adjoint) colour_mul_f64_k<18, true><<<g4, b4, 0, st>>>(g, o, i, u, hb, mu, tpp);
+            else colour_mul_f64_k<18, false><<<g4, b4, 0, st>>>(g, o, i, u, hb, mu, tpp);
+        } else {
+            if (adjoint) colour_mul_f64_k<12, true><<<g4, b4, 0, st>>>(g, o, i, u, hb, mu, tpp);
+            else colour_mul_f64_k<12, false><<<g4, b4, 0, st>>>(g, o, i, u, hb, mu, tpp);
+        }
+    } else if (prec == LQCD_F64) {
         if (link == 18) { LQCD_CMUL(LQCD_F64, 18) }
         else { LQCD_CMUL(LQCD_F64, 12) }
     } else {
