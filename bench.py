@@ -92,20 +92,14 @@ def measured_traffic(lattice, variant):
     return float(m_b.group(1))
 
 
-def cpu_baseline(lattice, budget_s=12.0, cg=None):
-    """The FP64 oracle's even-odd hop timed on the host on a bounded sample,
-    and (with the GPU solve's figures in `cg`) one application of the 32^4
-    normal operator A = Mhat^dag Mhat, the oracle CG's work per iteration,
-    scaled by the GPU's iteration count."""
-    import numpy as np
-    import torch
-
+def oracle_hops(lattice, budget_s):
+    """Apply the FP64 oracle's even-odd operator (D_eo then D_oe) on the
+    host for about budget_s seconds: (applications, wall s, CPU s)."""
     import lattice_inputs as LI
     from oracle import dirac
 
     U, psi = LI.workload_fields(1, lattice)
     psi_o = dirac.project(psi, 1)
-    vh = LI.volume(lattice) // 2
     n = 0
     w0, c0 = time.perf_counter(), time.process_time()
     while True:
@@ -114,12 +108,78 @@ def cpu_baseline(lattice, budget_s=12.0, cg=None):
         n += 1
         if time.perf_counter() - w0 > budget_s:
             break
-    wall = time.perf_counter() - w0
-    cpu = time.process_time() - c0
-    out = {"value": round(FLOP_SITE * 2 * vh * n / wall / 1e9, 4), "unit": "GFlop/s",
-           "cores": max(1, int(round(cpu / wall))), "host_cores": os.cpu_count(), "kind": "oracle",
-           "sample": f"{n} applications of the even-odd operator (D_eo then D_oe) on "
-                     f"{'x'.join(map(str, lattice))}, FP64 numpy oracle, {wall:.1f} s wall"}
+    return n, time.perf_counter() - w0, time.process_time() - c0
+
+
+def host_cpus() -> int:
+    """Cores this process may run on, at most 16 (one GPU's share of the
+    machine's cores)."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(16, n))
+
+
+def oracle_all_cores(lattice, budget_s):
+    """The same oracle loop in one single-threaded process per host core,
+    all at once (child processes that never touch the GPU): aggregate
+    GFlop/s and the processes used."""
+    import subprocess
+
+    k = host_cpus()
+    env = dict(os.environ, OMP_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1", MKL_NUM_THREADS="1")
+    lat = ",".join(map(str, lattice))
+    procs = [subprocess.Popen([sys.executable, os.path.abspath(__file__), "--cpu-worker", lat,
+                               str(budget_s)], stdout=subprocess.PIPE, stderr=subprocess.DEVNULL,
+                              env=env, text=True) for _ in range(k)]
+    vh = 1
+    for d in lattice:
+        vh *= d
+    vh //= 2
+    total, walls, done = 0.0, [], 0
+    for pr in procs:
+        try:
+            o, _ = pr.communicate(timeout=budget_s + 120)
+        except subprocess.TimeoutExpired:
+            pr.kill()
+            pr.communicate()
+            continue
+        if pr.returncode != 0 or not o.strip():
+            continue
+        r = json.loads(o.strip().splitlines()[-1])
+        total += FLOP_SITE * 2 * vh * r["n"] / r["wall"] / 1e9
+        walls.append(r["wall"])
+        done += 1
+    return {"value": round(total, 4), "unit": "GFlop/s", "cores": done, "processes": k,
+            "sample": f"{done} single-threaded processes, each applying the even-odd operator "
+                      f"to its own {'x'.join(map(str, lattice))} field for "
+                      f"{max(walls) if walls else 0:.1f} s, all at once: aggregate rate"}
+
+
+def cpu_baseline(lattice, budget_s=12.0, cg=None):
+    """The FP64 oracle's even-odd hop timed on the host on a bounded sample,
+    on all host cores at once (one process per core) and in one thread, and
+    (with the GPU solve's figures in `cg`) one application of the 32^4 normal
+    operator A = Mhat^dag Mhat, the oracle CG's work per iteration, scaled by
+    the GPU's iteration count."""
+    import torch
+
+    import lattice_inputs as LI
+    from oracle import dirac
+
+    vh = LI.volume(lattice) // 2
+    n, wall, cpu = oracle_hops(lattice, budget_s)
+    single = {"value": round(FLOP_SITE * 2 * vh * n / wall / 1e9, 4), "unit": "GFlop/s",
+              "cores": max(1, int(round(cpu / wall))),
+              "sample": f"{n} applications of the even-odd operator (D_eo then D_oe) on "
+                        f"{'x'.join(map(str, lattice))}, FP64 numpy oracle, {wall:.1f} s wall"}
+    # about 2 s per process: all cores together do a few times the CPU work
+    # of the single-thread sample, in a sixth of its wall time
+    allc = oracle_all_cores(lattice, 2.0)
+    out = {"value": allc["value"], "unit": "GFlop/s", "cores": allc["cores"],
+           "host_cores": os.cpu_count(), "kind": "oracle", "sample": allc["sample"],
+           "single_thread": single}
     if cg is not None:
         dims = tuple(cg["lattice"])
         Ud, pd = LI.workload_fields_device(3, dims, "cuda")
@@ -181,7 +241,15 @@ def main():
                     help="only time <a,b> and |a|^2 on the lattice and count distinct results")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB 5 times (counter calibration)")
+    ap.add_argument("--cpu-worker", nargs=2, metavar=("LATTICE", "SECONDS"), default=None,
+                    help=argparse.SUPPRESS)
     args = ap.parse_args()
+    if args.cpu_worker:
+        # one process of the all-cores oracle baseline (host only, no GPU)
+        lat = tuple(int(v) for v in args.cpu_worker[0].split(","))
+        n, wall, cpu = oracle_hops(lat, float(args.cpu_worker[1]))
+        print(json.dumps({"n": n, "wall": wall, "cpu": cpu}))
+        return
     if args.calibrate_copy:
         import torch
         n = args.calibrate_copy << 20
