@@ -19,7 +19,9 @@ moving the headline launch's algorithmic bytes on a lattice of the same
 extent ("copy_same_bytes"); "split" times the hop of one GPU's share of
 a t decomposition (48^3x12) split into face pack, face exchange, interior
 and boundary launches; "grad" times the differentiated
-operator (forward M psi, backward M^dag g and link force) on 24^4.
+operator (forward M psi, backward M^dag g and link force) on 24^4;
+"cpu_baseline" is the FP64 oracle's even-odd operator on the host, on all
+its cores at once (one single-threaded process per core) and in one thread.
 
 Timing: one step is captured into a HIP graph (torch.cuda.CUDAGraph around
 the library calls) and replayed; HIP events on the stream the graph is
